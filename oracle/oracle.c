@@ -1,0 +1,664 @@
+/*
+ * FP64 CPU oracle of the coupled immersed-boundary lattice-Boltzmann timestep
+ * of Tan, Sinno & Diamond, "A parallel fluid solid coupling model using LAMMPS
+ * and Palabos based on the immersed boundary method" (arXiv:1704.04551).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, plain reference that the
+ * GPU library is checked against.  Only the test-suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load it; the product path never does.
+ * It shares no source with the GPU library: every table, constant and formula
+ * below is written out here on its own.
+ *
+ * What it computes (all in double precision, plain loops):
+ *   Sec. 2.1  D3Q19 lattice-BGK with the forcing term of Eq. (4):
+ *             Eq. (1) evolution, Eq. (2) equilibrium, Eq. (3) moments with the
+ *             half-force shift, Eq. (5) tau-viscosity relation.
+ *   Sec. 2.2  membrane forces: linear springs 1/2 ks (l - l0)^2 per edge and the
+ *             dihedral bending energy of Eq. (8), F = -dE/dX.
+ *   Sec. 2.3  Eq. (14) velocity interpolation, Eq. (15) force spreading, with
+ *             the cosine kernel of Eq. (16) or Peskin's 4-point kernel.
+ *
+ * Readings taken where the paper is silent (each is also listed in the design
+ * notes of the repository):
+ *   - step order: forces at X^n -> spread -> moments (u^n includes g^n/2) ->
+ *     interpolate u^n at X^n -> X^{n+1} = X^n + U -> collide -> stream;
+ *   - walls: a wall axis has solid layers at index 0 and n-1; halfway
+ *     bounce-back with the moving-wall term -6 w_i rho_w (c_i . u_w), rho_w = 1;
+ *   - spreading drops shares that land on solid cells; interpolation reads the
+ *     wall velocity at solid cells;
+ *   - node positions are kept unwrapped; stencil cells wrap on periodic axes;
+ *   - bending angle: signed angle between the outward normals of the two
+ *     triangles sharing an edge, positive where the surface is convex.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#include <stdint.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* D3Q19 velocity set: one rest velocity, 6 face and 12 edge neighbours.     */
+/* Weights 1/3, 1/18, 1/36 (textbook D3Q19, the lattice named in Sec. 2.1).  */
+/* ------------------------------------------------------------------------ */
+static const int OC[19][3] = {
+    {0, 0, 0},
+    {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0},
+    {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+    {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+
+static double ow(int i) {
+  int s = abs(OC[i][0]) + abs(OC[i][1]) + abs(OC[i][2]);
+  if (s == 0) return 1.0 / 3.0;
+  if (s == 1) return 1.0 / 18.0;
+  return 1.0 / 36.0;
+}
+
+static int oopp(int i) {
+  for (int j = 0; j < 19; ++j)
+    if (OC[j][0] == -OC[i][0] && OC[j][1] == -OC[i][1] && OC[j][2] == -OC[i][2])
+      return j;
+  return -1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Discrete delta kernels, Sec. 2.3.                                         */
+/* ------------------------------------------------------------------------ */
+enum { ODELTA_COS = 0, ODELTA_PESKIN4 = 1 };
+
+/* One-dimensional kernel phi(r). kind 0: Eq. (16), 1/4 (1 + cos(pi r / 2)) for
+ * |r| <= 2.  kind 1: Peskin's 4-point kernel (Peskin 2002, cited in Sec. 2.3):
+ * (3 - 2|r| + sqrt(1 + 4|r| - 4 r^2)) / 8 for |r| <= 1,
+ * (5 - 2|r| - sqrt(-7 + 12|r| - 4 r^2)) / 8 for 1 <= |r| <= 2. */
+double oracle_phi(int kind, double r) {
+  double a = fabs(r);
+  if (a > 2.0) return 0.0;
+  if (kind == ODELTA_COS) return 0.25 * (1.0 + cos(M_PI * r / 2.0));
+  if (a <= 1.0) return (3.0 - 2.0 * a + sqrt(1.0 + 4.0 * a - 4.0 * a * a)) / 8.0;
+  {
+    double q = -7.0 + 12.0 * a - 4.0 * a * a;
+    if (q < 0.0) q = 0.0; /* a == 2 exactly gives q = 0; guard rounding */
+    return (5.0 - 2.0 * a - sqrt(q)) / 8.0;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Membrane template: topology from outward (counter-clockwise) triangles.   */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int nn, nt, ne;
+  int *tri;      /* [nt][3] */
+  int *ev;       /* [ne][4]: v0, v1, v2, v3 ; shared edge v1-v2,
+                    v0 opposite in the triangle holding v1->v2,
+                    v3 opposite in the triangle holding v2->v1 */
+  double *l0;    /* [ne] rest length */
+  double *th0;   /* [ne] rest bending angle */
+} otmpl;
+
+static void cross3(const double *a, const double *b, double *c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+static double dot3(const double *a, const double *b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Build the edge list.  Every directed edge of a closed, consistently
+ * oriented manifold appears in exactly one triangle, and its reverse in
+ * exactly one other.  Returns 0, or -1 for a mesh that is not such a surface. */
+static int tmpl_build(otmpl *T, int nn, int nt, const int *tri) {
+  T->nn = nn;
+  T->nt = nt;
+  T->tri = (int *)malloc(sizeof(int) * 3 * (size_t)nt);
+  memcpy(T->tri, tri, sizeof(int) * 3 * (size_t)nt);
+  /* directed-edge table: for each triangle side (p->q), the opposite vertex */
+  int nd = 3 * nt;
+  int *dp = (int *)malloc(sizeof(int) * nd), *dq = (int *)malloc(sizeof(int) * nd),
+      *dr = (int *)malloc(sizeof(int) * nd);
+  for (int t = 0; t < nt; ++t)
+    for (int s = 0; s < 3; ++s) {
+      int p = tri[3 * t + s], q = tri[3 * t + (s + 1) % 3], r = tri[3 * t + (s + 2) % 3];
+      if (p < 0 || p >= nn || q < 0 || q >= nn || r < 0 || r >= nn || p == q || q == r || p == r) {
+        free(dp); free(dq); free(dr);
+        return -1;
+      }
+      dp[3 * t + s] = p; dq[3 * t + s] = q; dr[3 * t + s] = r;
+    }
+  /* each undirected edge once, taken from its directed copy with p < q */
+  T->ne = 0;
+  T->ev = (int *)malloc(sizeof(int) * 4 * (size_t)nd);
+  int ok = 0;
+  for (int a = 0; a < nd; ++a) {
+    /* count copies of a's direction and of its reverse */
+    int same = 0, rev = -1, nrev = 0;
+    for (int b = 0; b < nd; ++b) {
+      if (dp[b] == dp[a] && dq[b] == dq[a]) ++same;
+      if (dp[b] == dq[a] && dq[b] == dp[a]) { rev = b; ++nrev; }
+    }
+    if (same != 1 || nrev != 1) { ok = -1; break; }
+    if (dp[a] < dq[a]) {
+      int *e = T->ev + 4 * T->ne;
+      e[0] = dr[a];    /* v0: opposite vertex of the triangle with v1->v2 */
+      e[1] = dp[a];    /* v1 */
+      e[2] = dq[a];    /* v2 */
+      e[3] = dr[rev];  /* v3: opposite vertex of the triangle with v2->v1 */
+      T->ne++;
+    }
+  }
+  free(dp); free(dq); free(dr);
+  if (ok != 0) return -1;
+  T->l0 = (double *)calloc((size_t)T->ne, sizeof(double));
+  T->th0 = (double *)calloc((size_t)T->ne, sizeof(double));
+  return 0;
+}
+
+/* Signed angle between the outward normals of the two triangles of an edge
+ * (Eq. (8) uses the angle formed by the two outward surface normals).
+ * nA = (v2 - v1) x (v0 - v1), nB = (v1 - v2) x (v3 - v2); the sign is that of
+ * (nA x nB) . (v2 - v1): positive where the surface bends outward (convex). */
+static double dihedral_angle(const double *v0, const double *v1, const double *v2,
+                             const double *v3) {
+  double e[3], a[3], b[3], nA[3], nB[3], m[3];
+  for (int k = 0; k < 3; ++k) {
+    e[k] = v2[k] - v1[k];
+    a[k] = v0[k] - v1[k];
+    b[k] = v3[k] - v2[k];
+  }
+  double me[3] = {-e[0], -e[1], -e[2]};
+  cross3(e, a, nA);
+  cross3(me, b, nB);
+  cross3(nA, nB, m);
+  double le = sqrt(dot3(e, e));
+  double s = dot3(m, e) / le;  /* |nA||nB| sin(theta) */
+  double c = dot3(nA, nB);     /* |nA||nB| cos(theta) */
+  return atan2(s, c);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Membrane energy and force, Sec. 2.2.                                      */
+/*   E = sum_edges 1/2 ks (l - l0)^2 + sum_edges kb (1 - cos(theta - theta0)) */
+/*   F_k = -dE/dX_k.                                                          */
+/* The bending gradient uses the closed form of the dihedral-angle gradient:  */
+/* with e = v2 - v1, L = |e|, nA, nB as above:                                */
+/*   dtheta/dv0 = -L nA / |nA|^2,  dtheta/dv3 = -L nB / |nB|^2,               */
+/*   dtheta/dv1 = -(1 - t0) dtheta/dv0 - (1 - t3) dtheta/dv3,                 */
+/*   dtheta/dv2 = -t0 dtheta/dv0 - t3 dtheta/dv3,                             */
+/* where t0 = (v0 - v1).e / L^2 and t3 = (v3 - v1).e / L^2.                   */
+/* ------------------------------------------------------------------------ */
+static void tmpl_rest(otmpl *T, const double *xr) {
+  for (int j = 0; j < T->ne; ++j) {
+    const int *e = T->ev + 4 * j;
+    const double *v0 = xr + 3 * e[0], *v1 = xr + 3 * e[1], *v2 = xr + 3 * e[2],
+                 *v3 = xr + 3 * e[3];
+    double d[3] = {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]};
+    T->l0[j] = sqrt(dot3(d, d));
+    T->th0[j] = dihedral_angle(v0, v1, v2, v3);
+  }
+}
+
+/* Adds the membrane force of one mesh to F (both [nn][3]); returns energy. */
+static double membrane_force(const otmpl *T, const double *x, double ks, double kb, double *F) {
+  double E = 0.0;
+  for (int j = 0; j < T->ne; ++j) {
+    const int *ev = T->ev + 4 * j;
+    const double *v0 = x + 3 * ev[0], *v1 = x + 3 * ev[1], *v2 = x + 3 * ev[2],
+                 *v3 = x + 3 * ev[3];
+    /* spring on edge v1-v2 */
+    double d[3] = {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]};
+    double l = sqrt(dot3(d, d));
+    double dl = l - T->l0[j];
+    E += 0.5 * ks * dl * dl;
+    for (int k = 0; k < 3; ++k) {
+      double fk = ks * dl * d[k] / l;  /* dE/dv2 = ks dl d/l ; force on v2 = -that */
+      F[3 * ev[1] + k] += fk;
+      F[3 * ev[2] + k] -= fk;
+    }
+    /* dihedral bending on the same edge */
+    if (kb != 0.0) {
+      double th = dihedral_angle(v0, v1, v2, v3);
+      E += kb * (1.0 - cos(th - T->th0[j]));
+      double dEdth = kb * sin(th - T->th0[j]);
+      double e[3], a[3], b[3], nA[3], nB[3];
+      for (int k = 0; k < 3; ++k) {
+        e[k] = v2[k] - v1[k];
+        a[k] = v0[k] - v1[k];
+        b[k] = v3[k] - v2[k];
+      }
+      double me[3] = {-e[0], -e[1], -e[2]};
+      cross3(e, a, nA);
+      cross3(me, b, nB);
+      double L2 = dot3(e, e), L = sqrt(L2);
+      double nA2 = dot3(nA, nA), nB2 = dot3(nB, nB);
+      double t0 = dot3(a, e) / L2;
+      double v3v1[3] = {v3[0] - v1[0], v3[1] - v1[1], v3[2] - v1[2]};
+      double t3 = dot3(v3v1, e) / L2;
+      for (int k = 0; k < 3; ++k) {
+        double g0 = -L * nA[k] / nA2;
+        double g3 = -L * nB[k] / nB2;
+        double g1 = -(1.0 - t0) * g0 - (1.0 - t3) * g3;
+        double g2 = -t0 * g0 - t3 * g3;
+        F[3 * ev[0] + k] -= dEdth * g0;
+        F[3 * ev[1] + k] -= dEdth * g1;
+        F[3 * ev[2] + k] -= dEdth * g2;
+        F[3 * ev[3] + k] -= dEdth * g3;
+      }
+    }
+  }
+  return E;
+}
+
+static void tmpl_free(otmpl *T) {
+  free(T->tri); free(T->ev); free(T->l0); free(T->th0);
+  memset(T, 0, sizeof(*T));
+}
+
+/* Stand-alone membrane force for pinning tests: topology from tris, rest
+ * state from xref, force and energy at x.  Returns #edges, or -1 on a bad mesh. */
+int oracle_membrane(int nn, int nt, const int *tri, const double *xref, const double *x,
+                    double ks, double kb, double *F, double *E) {
+  otmpl T;
+  memset(&T, 0, sizeof(T));
+  if (tmpl_build(&T, nn, nt, tri) != 0) { tmpl_free(&T); return -1; }
+  tmpl_rest(&T, xref);
+  memset(F, 0, sizeof(double) * 3 * (size_t)nn);
+  double e = membrane_force(&T, x, ks, kb, F);
+  if (E) *E = e;
+  int ne = T.ne;
+  tmpl_free(&T);
+  return ne;
+}
+
+/* Edge list and rest data (v0,v1,v2,v3 per edge, l0, theta0) for tests. */
+int oracle_mesh_edges(int nn, int nt, const int *tri, const double *xref, int *ev_out,
+                      double *l0_out, double *th0_out) {
+  otmpl T;
+  memset(&T, 0, sizeof(T));
+  if (tmpl_build(&T, nn, nt, tri) != 0) { tmpl_free(&T); return -1; }
+  tmpl_rest(&T, xref);
+  if (ev_out) memcpy(ev_out, T.ev, sizeof(int) * 4 * (size_t)T.ne);
+  if (l0_out) memcpy(l0_out, T.l0, sizeof(double) * (size_t)T.ne);
+  if (th0_out) memcpy(th0_out, T.th0, sizeof(double) * (size_t)T.ne);
+  int ne = T.ne;
+  tmpl_free(&T);
+  return ne;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Lattice geometry.                                                         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int n[3];
+  int wall[3];           /* 1: solid layers at 0 and n-1 on this axis */
+  double ulo[3][3];      /* velocity of the wall layer at index 0, per axis */
+  double uhi[3][3];      /* velocity of the wall layer at index n-1, per axis */
+} ogeom;
+
+static long cidx(const ogeom *G, int x, int y, int z) {
+  return (long)x + (long)G->n[0] * ((long)y + (long)G->n[1] * (long)z);
+}
+
+static int wrapi(int v, int n) {
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+/* Is cell (x,y,z) (already inside the array) solid?  If so, its velocity. */
+static int solid_at(const ogeom *G, const int c[3], double uw[3]) {
+  for (int a = 0; a < 3; ++a) {
+    if (!G->wall[a]) continue;
+    if (c[a] == 0 || c[a] == G->n[a] - 1) {
+      const double *v = (c[a] == 0) ? G->ulo[a] : G->uhi[a];
+      if (uw) { uw[0] = v[0]; uw[1] = v[1]; uw[2] = v[2]; }
+      return 1;
+    }
+  }
+  return 0;
+}
+
+/* Stencil of a node on one axis: base floor(X) - 1 ... floor(X) + 2 (four
+ * points; the kernel vanishes at distance 2).  On a wall axis a node must lie
+ * in [1, n-2) so that every stencil cell is inside the array.  Returns 0, or
+ * -1 for a node outside that range. */
+static int stencil_axis(const ogeom *G, int a, double X, int cell[4], double r[4]) {
+  double fb = floor(X);
+  long b = (long)fb;
+  if (G->wall[a]) {
+    if (!(X >= 1.0 && X < (double)(G->n[a] - 2))) return -1;
+  }
+  for (int s = 0; s < 4; ++s) {
+    long c = b - 1 + s;
+    r[s] = (double)c - X;
+    cell[s] = G->wall[a] ? (int)c : wrapi((int)(c % G->n[a]), G->n[a]);
+  }
+  return 0;
+}
+
+/* Eq. (15): g(x) += sum_k F_k delta(x - X_k), delta = phi phi phi (Eq. (16)).
+ * Nodes are visited in ascending order; shares on solid cells are dropped.
+ * g is [3][ncell].  Returns 0, or -1 if a node is outside the admissible range. */
+static int spread(const ogeom *G, int kind, int nn, const double *X, const double *F, double *g) {
+  long nc = (long)G->n[0] * G->n[1] * G->n[2];
+  for (int k = 0; k < nn; ++k) {
+    int cx[4], cy[4], cz[4];
+    double rx[4], ry[4], rz[4];
+    if (stencil_axis(G, 0, X[3 * k + 0], cx, rx) || stencil_axis(G, 1, X[3 * k + 1], cy, ry) ||
+        stencil_axis(G, 2, X[3 * k + 2], cz, rz))
+      return -1;
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int l = 0; l < 4; ++l) {
+          int c[3] = {cx[i], cy[j], cz[l]};
+          if (solid_at(G, c, NULL)) continue;
+          double w = oracle_phi(kind, rx[i]) * oracle_phi(kind, ry[j]) * oracle_phi(kind, rz[l]);
+          long id = cidx(G, c[0], c[1], c[2]);
+          for (int a = 0; a < 3; ++a) g[a * nc + id] += w * F[3 * k + a];
+        }
+  }
+  return 0;
+}
+
+/* Eq. (14): U_k = sum_x u(x) delta(x - X_k); a solid stencil cell contributes
+ * its wall velocity.  u is [3][ncell]; U is [nn][3]. */
+static int interp(const ogeom *G, int kind, int nn, const double *X, const double *u, double *U) {
+  long nc = (long)G->n[0] * G->n[1] * G->n[2];
+  for (int k = 0; k < nn; ++k) {
+    int cx[4], cy[4], cz[4];
+    double rx[4], ry[4], rz[4];
+    if (stencil_axis(G, 0, X[3 * k + 0], cx, rx) || stencil_axis(G, 1, X[3 * k + 1], cy, ry) ||
+        stencil_axis(G, 2, X[3 * k + 2], cz, rz))
+      return -1;
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i)
+      for (int j = 0; j < 4; ++j)
+        for (int l = 0; l < 4; ++l) {
+          int c[3] = {cx[i], cy[j], cz[l]};
+          double w = oracle_phi(kind, rx[i]) * oracle_phi(kind, ry[j]) * oracle_phi(kind, rz[l]);
+          double uw[3];
+          if (solid_at(G, c, uw)) {
+            for (int a = 0; a < 3; ++a) s[a] += w * uw[a];
+          } else {
+            long id = cidx(G, c[0], c[1], c[2]);
+            for (int a = 0; a < 3; ++a) s[a] += w * u[a * nc + id];
+          }
+        }
+    for (int a = 0; a < 3; ++a) U[3 * k + a] = s[a];
+  }
+  return 0;
+}
+
+static void geom_set(ogeom *G, const int n[3], const int wall[3], const double *ulo,
+                     const double *uhi) {
+  for (int a = 0; a < 3; ++a) {
+    G->n[a] = n[a];
+    G->wall[a] = wall ? wall[a] : 0;
+    for (int b = 0; b < 3; ++b) {
+      G->ulo[a][b] = ulo ? ulo[3 * a + b] : 0.0;
+      G->uhi[a][b] = uhi ? uhi[3 * a + b] : 0.0;
+    }
+  }
+}
+
+/* Stand-alone spreading onto a box (for adjointness and brute-force pins). */
+int oracle_spread_field(const int n[3], const int wall[3], int kind, int nn, const double *X,
+                        const double *F, double *g) {
+  ogeom G;
+  geom_set(&G, n, wall, NULL, NULL);
+  memset(g, 0, sizeof(double) * 3 * (size_t)n[0] * n[1] * n[2]);
+  return spread(&G, kind, nn, X, F, g);
+}
+
+/* Stand-alone interpolation from a given velocity field. */
+int oracle_interp_field(const int n[3], const int wall[3], const double *ulo, const double *uhi,
+                        int kind, int nn, const double *X, const double *u, double *U) {
+  ogeom G;
+  geom_set(&G, n, wall, ulo, uhi);
+  return interp(&G, kind, nn, X, u, U);
+}
+
+/* ------------------------------------------------------------------------ */
+/* The coupled simulation.                                                   */
+/* ------------------------------------------------------------------------ */
+typedef struct { int tmpl, off, nn; double ks, kb; } omesh;
+
+typedef struct osim {
+  ogeom G;
+  long nc;
+  double tau, gb[3];
+  int kind;
+  double *f, *fn;       /* [19][nc] populations (post-streaming, pre-collision) */
+  double *g;            /* [3][nc] spread IB force density */
+  double *rho, *u;      /* moments of the current step */
+  unsigned char *solid; /* [nc] */
+  int ntm, nme, nnode, cap_nodes;
+  otmpl *tm;
+  omesh *me;
+  double *X, *F, *U;    /* [nnode][3] */
+  long step;
+  int err;
+} osim;
+
+static double feq(int i, double rho, const double u[3]) {
+  double cu = OC[i][0] * u[0] + OC[i][1] * u[1] + OC[i][2] * u[2];
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  /* Eq. (2) with cs^2 = 1/3 */
+  return ow(i) * rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
+}
+
+/* init_profile 0: fluid at rest; 1: the linear (Couette) profile between the
+ * walls of the single wall axis, wall layers at 0 and n-1, effective walls at
+ * 0.5 and n-1.5.  f = f_eq(rho = 1, u0), Sec. 2.1. */
+osim *oracle_sim_create(const int n[3], double tau, const double gb[3], const int wall[3],
+                        const double *ulo, const double *uhi, int kind, int init_profile) {
+  if (tau <= 0.5) return NULL;
+  for (int a = 0; a < 3; ++a)
+    if (n[a] < 4) return NULL;
+  osim *S = (osim *)calloc(1, sizeof(osim));
+  geom_set(&S->G, n, wall, ulo, uhi);
+  S->nc = (long)n[0] * n[1] * n[2];
+  S->tau = tau;
+  for (int a = 0; a < 3; ++a) S->gb[a] = gb ? gb[a] : 0.0;
+  S->kind = kind;
+  S->f = (double *)calloc(19 * (size_t)S->nc, sizeof(double));
+  S->fn = (double *)calloc(19 * (size_t)S->nc, sizeof(double));
+  S->g = (double *)calloc(3 * (size_t)S->nc, sizeof(double));
+  S->rho = (double *)calloc((size_t)S->nc, sizeof(double));
+  S->u = (double *)calloc(3 * (size_t)S->nc, sizeof(double));
+  S->solid = (unsigned char *)calloc((size_t)S->nc, 1);
+  int pa = -1;
+  for (int a = 0; a < 3; ++a)
+    if (S->G.wall[a]) pa = a;
+  for (int z = 0; z < n[2]; ++z)
+    for (int y = 0; y < n[1]; ++y)
+      for (int x = 0; x < n[0]; ++x) {
+        int c[3] = {x, y, z};
+        long id = cidx(&S->G, x, y, z);
+        S->solid[id] = (unsigned char)solid_at(&S->G, c, NULL);
+        double u0[3] = {0.0, 0.0, 0.0};
+        if (init_profile == 1 && pa >= 0) {
+          double H = (double)(n[pa] - 2);
+          double s = ((double)c[pa] - 0.5) / H;
+          for (int b = 0; b < 3; ++b) u0[b] = S->G.ulo[pa][b] + (S->G.uhi[pa][b] - S->G.ulo[pa][b]) * s;
+        }
+        for (int i = 0; i < 19; ++i) S->f[i * S->nc + id] = S->solid[id] ? 0.0 : feq(i, 1.0, u0);
+      }
+  return S;
+}
+
+void oracle_sim_destroy(osim *S) {
+  if (!S) return;
+  for (int t = 0; t < S->ntm; ++t) tmpl_free(&S->tm[t]);
+  free(S->tm); free(S->me);
+  free(S->f); free(S->fn); free(S->g); free(S->rho); free(S->u); free(S->solid);
+  free(S->X); free(S->F); free(S->U);
+  free(S);
+}
+
+int oracle_template_add(osim *S, int nn, int nt, const int *tri, const double *xref) {
+  S->tm = (otmpl *)realloc(S->tm, sizeof(otmpl) * (size_t)(S->ntm + 1));
+  otmpl *T = &S->tm[S->ntm];
+  memset(T, 0, sizeof(*T));
+  if (tmpl_build(T, nn, nt, tri) != 0) { tmpl_free(T); return -1; }
+  tmpl_rest(T, xref);
+  return S->ntm++;
+}
+
+int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
+  if (tmpl < 0 || tmpl >= S->ntm) return -1;
+  int nn = S->tm[tmpl].nn;
+  S->me = (omesh *)realloc(S->me, sizeof(omesh) * (size_t)(S->nme + 1));
+  omesh *M = &S->me[S->nme];
+  M->tmpl = tmpl; M->off = S->nnode; M->nn = nn; M->ks = ks; M->kb = kb;
+  S->X = (double *)realloc(S->X, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->F = (double *)realloc(S->F, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->U = (double *)realloc(S->U, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  memcpy(S->X + 3 * (size_t)S->nnode, x, sizeof(double) * 3 * (size_t)nn);
+  memset(S->F + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
+  memset(S->U + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
+  S->nnode += nn;
+  return S->nme++;
+}
+
+/* Steps 1-4 of a timestep at the current state (no mutation of f or X):
+ * membrane forces F(X^n), spread g^n, moments rho^n, u^n (Eq. (3) with the
+ * total force g_body + g^n), interpolated node velocities U^n. */
+static int observe(osim *S) {
+  long nc = S->nc;
+  memset(S->F, 0, sizeof(double) * 3 * (size_t)S->nnode);
+  for (int m = 0; m < S->nme; ++m) {
+    const omesh *M = &S->me[m];
+    membrane_force(&S->tm[M->tmpl], S->X + 3 * (size_t)M->off, M->ks, M->kb, S->F + 3 * (size_t)M->off);
+  }
+  memset(S->g, 0, sizeof(double) * 3 * (size_t)nc);
+  if (spread(&S->G, S->kind, S->nnode, S->X, S->F, S->g) != 0) return -1;
+#pragma omp parallel for schedule(static)
+  for (long id = 0; id < nc; ++id) {
+    if (S->solid[id]) {
+      S->rho[id] = 0.0;
+      S->u[id] = S->u[nc + id] = S->u[2 * nc + id] = 0.0;
+      continue;
+    }
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+      double fi = S->f[i * nc + id];
+      rho += fi;
+      for (int a = 0; a < 3; ++a) j[a] += fi * OC[i][a];
+    }
+    S->rho[id] = rho;
+    for (int a = 0; a < 3; ++a) S->u[a * nc + id] = (j[a] + 0.5 * (S->gb[a] + S->g[a * nc + id])) / rho;
+  }
+  if (interp(&S->G, S->kind, S->nnode, S->X, S->u, S->U) != 0) return -1;
+  return 0;
+}
+
+/* One timestep, in the order documented at the top of this file. */
+static int step1(osim *S) {
+  if (observe(S) != 0) return -1;
+  long nc = S->nc;
+  const int *n = S->G.n;
+  /* node update X^{n+1} = X^n + U^n (unit time step) */
+  for (long k = 0; k < 3L * S->nnode; ++k) S->X[k] += S->U[k];
+  double om = 1.0 / S->tau, pre = 1.0 - 0.5 / S->tau;
+#pragma omp parallel for schedule(static)
+  for (int z = 0; z < n[2]; ++z)
+    for (int y = 0; y < n[1]; ++y)
+      for (int x = 0; x < n[0]; ++x) {
+        long id = cidx(&S->G, x, y, z);
+        if (S->solid[id]) continue;
+        double rho = S->rho[id];
+        double u[3] = {S->u[id], S->u[nc + id], S->u[2 * nc + id]};
+        double g[3];
+        for (int a = 0; a < 3; ++a) g[a] = S->gb[a] + S->g[a * nc + id];
+        double ug = u[0] * g[0] + u[1] * g[1] + u[2] * g[2];
+        for (int i = 0; i < 19; ++i) {
+          double fi = S->f[i * nc + id];
+          double cu = OC[i][0] * u[0] + OC[i][1] * u[1] + OC[i][2] * u[2];
+          double cg = OC[i][0] * g[0] + OC[i][1] * g[1] + OC[i][2] * g[2];
+          /* Eq. (4): (1 - 1/(2 tau)) w_i [ (c_i - u)/cs^2 + (c_i.u) c_i / cs^4 ] . g */
+          double Fi = pre * ow(i) * (3.0 * (cg - ug) + 9.0 * cu * cg);
+          /* Eq. (1): BGK relaxation plus forcing */
+          double fs = fi - om * (fi - feq(i, rho, u)) + Fi;
+          /* streaming with periodic wrap and halfway bounce-back */
+          int c[3] = {x + OC[i][0], y + OC[i][1], z + OC[i][2]};
+          for (int a = 0; a < 3; ++a)
+            if (!S->G.wall[a]) c[a] = wrapi(c[a], n[a]);
+          double uw[3];
+          if (solid_at(&S->G, c, uw)) {
+            double cuw = OC[i][0] * uw[0] + OC[i][1] * uw[1] + OC[i][2] * uw[2];
+            S->fn[oopp(i) * nc + id] = fs - 6.0 * ow(i) * 1.0 * cuw;
+          } else {
+            S->fn[i * nc + cidx(&S->G, c[0], c[1], c[2])] = fs;
+          }
+        }
+      }
+  double *t = S->f; S->f = S->fn; S->fn = t;
+  S->step++;
+  return 0;
+}
+
+int oracle_sim_step(osim *S, long nsteps) {
+  for (long s = 0; s < nsteps; ++s)
+    if (step1(S) != 0) { S->err = 1; return -1; }
+  return 0;
+}
+
+/* Observables at the current time N: rho, u (fluid cells; 0 at solid cells),
+ * g = g_body + spread IB force (fluid cells), each [ncell] / [3][ncell]. */
+int oracle_sim_observe(osim *S, double *rho, double *u, double *g) {
+  if (observe(S) != 0) return -1;
+  long nc = S->nc;
+  if (rho) memcpy(rho, S->rho, sizeof(double) * (size_t)nc);
+  if (u) memcpy(u, S->u, sizeof(double) * 3 * (size_t)nc);
+  if (g)
+    for (long id = 0; id < nc; ++id)
+      for (int a = 0; a < 3; ++a) g[a * nc + id] = S->solid[id] ? 0.0 : S->gb[a] + S->g[a * nc + id];
+  return 0;
+}
+
+/* Node state of one mesh at time N: X^N, U^N (interpolated with the force at
+ * X^N) and F^N, each [nn][3]. */
+int oracle_sim_nodes(osim *S, int mesh, double *X, double *U, double *F) {
+  if (mesh < 0 || mesh >= S->nme) return -1;
+  if (observe(S) != 0) return -1;
+  const omesh *M = &S->me[mesh];
+  size_t o = 3 * (size_t)M->off, c = sizeof(double) * 3 * (size_t)M->nn;
+  if (X) memcpy(X, S->X + o, c);
+  if (U) memcpy(U, S->U + o, c);
+  if (F) memcpy(F, S->F + o, c);
+  return M->nn;
+}
+
+/* Mass sum_fluid sum_i f_i and momentum sum_fluid sum_i f_i c_i of the
+ * stored populations. */
+void oracle_sim_conservation(osim *S, double *mass, double mom[3]) {
+  double m = 0.0, p[3] = {0.0, 0.0, 0.0};
+  for (long id = 0; id < S->nc; ++id) {
+    if (S->solid[id]) continue;
+    for (int i = 0; i < 19; ++i) {
+      double fi = S->f[i * S->nc + id];
+      m += fi;
+      for (int a = 0; a < 3; ++a) p[a] += fi * OC[i][a];
+    }
+  }
+  *mass = m;
+  for (int a = 0; a < 3; ++a) mom[a] = p[a];
+}
+
+/* Raw populations [19][ncell] in this file's velocity order (tests only). */
+void oracle_sim_populations(osim *S, double *f) {
+  memcpy(f, S->f, sizeof(double) * 19 * (size_t)S->nc);
+}
+
+/* Velocity set as used here, for tests that pin it. */
+void oracle_velocity_set(int *c, double *w) {
+  for (int i = 0; i < 19; ++i) {
+    for (int a = 0; a < 3; ++a) c[3 * i + a] = OC[i][a];
+    w[i] = ow(i);
+  }
+}
+
+long oracle_sim_stepcount(osim *S) { return S->step; }
+int oracle_sim_nnodes(osim *S) { return S->nnode; }
