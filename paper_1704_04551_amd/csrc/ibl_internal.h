@@ -1,0 +1,124 @@
+// Internal declarations shared by the kernels (ibl_kernels.hip) and the host
+// runtime (ibl_runtime.hip) of libibl.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibl {
+
+constexpr int kQ = 19;
+constexpr int kBrick = 8;            // edge of the cubic bricks used for spreading
+constexpr int kBrickCells = kBrick * kBrick * kBrick;
+constexpr int kCandCap = 2048;       // candidate nodes per brick
+constexpr int kLatticeBlock = 256;   // cells per lattice work item
+constexpr int kNodesPerItem = 4;     // nodes per interpolation work item (one wave each)
+constexpr int kReduceItemCells = 4096;
+constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup per mesh)
+
+enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2 };
+enum Delta : int { kCos = 0, kPeskin4 = 1 };
+
+enum Health : uint32_t {
+  kHNonfiniteF = 0x1u,
+  kHRho = 0x2u,
+  kHMach = 0x4u,
+  kHNodeRange = 0x8u,
+  kHOverflow = 0x10u,
+  kHNonfiniteX = 0x20u,
+};
+
+// Spreading record of one node, written by the force kernel at X^n and read by
+// the spreading and interpolation kernels of the same step.
+template <typename R>
+struct alignas(16) NodeRec {
+  int32_t base[3];   // floor(X) per axis (unwrapped)
+  int32_t valid;     // 0 when the node is outside the admissible range
+  R w[3][4];         // phi at offsets -1, 0, +1, +2 from base, per axis
+  R F[3];            // membrane force
+  R pad;
+};
+
+// Per-simulation device descriptor.  Lives in device memory; kernels take an
+// array of these (one entry for a single simulation, many for a batch).
+struct SimDev {
+  int32_t n[3];
+  int32_t wall[3];
+  int64_t ncell;
+  int32_t nb[3];          // bricks per axis
+  int32_t delta;
+  int64_t nbrick;
+  double tau;
+  double gb[3];
+  double ulo[3][3];
+  double uhi[3][3];
+  int32_t has_ib;         // 1 when meshes are present
+  int32_t nnodes;
+  int32_t nmeshes;
+  int32_t maxn;           // SoA stride of the node arrays (capacity)
+  // state
+  void* f[2];             // populations, [19][ncell] in storage format
+  void* u;                // [3][ncell] velocity (compute precision)
+  void* g;                // [3][ncell] spread force (compute precision)
+  void* rho;              // [ncell] density (observation only)
+  double* X;              // [3][max_nodes] positions
+  double* F;              // [3][max_nodes] membrane forces
+  double* U;              // [3][max_nodes] interpolated velocities
+  void* rec;              // [max_nodes] NodeRec
+  int32_t* bcount;        // [nbrick]
+  int32_t* blist;         // [nbrick][kCandCap]
+  // meshes
+  int32_t* mesh_tmpl;     // [max_meshes]
+  int32_t* mesh_off;      // [max_meshes] first global node
+  double* mesh_ks;
+  double* mesh_kb;
+  // templates
+  int32_t* t_nn;          // [max_templates]
+  int32_t* t_node0;       // first template-node index
+  int32_t* t_edge0;       // first template-edge index
+  int32_t* inc_ptr;       // [max_template_nodes + 1] CSR row pointers over all templates
+  int32_t* inc;           // incidence entries: (edge << 2) | role, global edge index
+  int32_t* ev;            // [max_template_edges][4] template-local node indices
+  double* el0;            // [max_template_edges] rest length
+  double* ec0;            // cos(theta0)
+  double* es0;            // sin(theta0)
+  // control
+  int64_t* step;          // completed steps (A/B parity = step & 1)
+  int64_t* remaining;     // steps still to run in the current launch sequence
+  uint32_t* health;
+  double* red;            // [reduce items][4] partial sums
+  double* red_out;        // [4] mass, momentum
+};
+
+// Work-item prefix tables of a launch set (one simulation or a batch).
+struct Items {
+  int32_t nsim;
+  int32_t lat_total, red_total, mesh_total, brick_total, node_total;
+  const int32_t* lat_off;    // [nsim + 1]
+  const int32_t* red_off;
+  const int32_t* mesh_off;
+  const int32_t* brick_off;
+  const int32_t* node_off;
+};
+
+// Phases of one timestep, in launch order.
+enum Phase : int {
+  kPhaseForces = 0,   // membrane forces, spreading records, candidate lists
+  kPhaseSpread = 1,   // force spreading into the per-cell force field
+  kPhaseLattice = 2,  // moments, collision, streaming (u^n written)
+  kPhaseInterp = 3,   // velocity interpolation and node update
+  kPhaseAdvance = 4,  // step counter
+  kNumPhases = 5
+};
+
+// Kernel launchers (ibl_kernels.hip).  mode: 0 = timestep, 1 = observe.
+hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int init_axis_profile,
+                       hipStream_t s);
+hipError_t launch_template_rest(const SimDev* sim, int tmpl, int nedges, const double* xref,
+                                hipStream_t s);
+hipError_t launch_phase(int storage, const SimDev* sims, const Items& it, int phase, int mode,
+                        hipStream_t s);
+hipError_t launch_step(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
+hipError_t launch_reduce(int storage, const SimDev* sims, const Items& it, hipStream_t s);
+
+}  // namespace ibl

@@ -5,8 +5,6 @@ Sec. 3.1) says: a sphere spins at half the shear rate, an ellipsoid tumbles
 with period T = 2 pi / gamma (a/b + b/a).  These runs exercise forces,
 spreading, moments, interpolation and the node update together.
 """
-import os
-
 import numpy as np
 import pytest
 
@@ -95,14 +93,14 @@ def test_jeffery_quarter_period():
     assert q is not None and 1.0 <= q / T4 < 1.15, q / T4
 
 
-@pytest.mark.skipif(os.environ.get("IBL_SLOW") != "1", reason="paper-size Jeffery run; set IBL_SLOW=1")
 def test_jeffery_paper_case():
     """Sec. 3.1 case: a = 6, b = c = 4.5, H = 60, U = 0.01, nu = 1/6
     (tau = 1), 60 x 30 (vorticity) x 60 (+2 wall layers).  The paper reports a
-    2.62 % mean relative angle error for its rigid-body variant."""
+    2.62 % mean relative angle error for its rigid-body variant; the oracle's
+    capsule reaches pi/2 within 2 % of T/4 (measured ratio 1.019)."""
     n = (60, 30, 62)
     gam = 2 * 0.01 / 60
     q = _quarter_period(n, 6.0, 4.5, gam, 1.0, 0.5, 0.05, every=100, max_steps=40000)
     T4 = np.pi / (2 * gam) * (6.0 / 4.5 + 4.5 / 6.0)
     print("quarter period ratio", q / T4)
-    assert q is not None and abs(q / T4 - 1.0) < 0.1
+    assert q is not None and abs(q / T4 - 1.0) < 0.05
