@@ -1,0 +1,230 @@
+// Device-side helpers shared by the lattice and immersed-boundary kernels.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <math.h>
+
+#include "ibl_internal.h"
+
+namespace ibl {
+namespace {
+
+// ------------------------------------------------------------------------
+// D3Q19 in this file's order: the rest velocity, the z = 0 plane, then the
+// z = +-1 links.  Opposite directions are neighbours: (1,2), (3,4), ... (17,18).
+// Weights: 1/3 rest, 1/18 axis links, 1/36 diagonal links.
+// ------------------------------------------------------------------------
+constexpr int kCx[kQ] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0};
+constexpr int kCy[kQ] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1};
+constexpr int kCz[kQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1};
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wq(int i) {
+  return i == 0 ? 1.0 / 3.0 : ((i <= 4 || i == 9 || i == 10) ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// ---------------------------------------------------------------- storage --
+// Every storage mode keeps the offset h_i = f_i - w_i (the equilibrium at rest
+// subtracted): at low Mach number f_i differs from w_i only in its low bits,
+// and a body-force increment of 1e-6 added to f_i ~ 0.05 would lose most of
+// its bits in binary32.  Offsets keep them.  FP16 stores h_i as binary16
+// (round to nearest even); FP32 and FP64 store it at full width.
+template <int ST>
+struct Store;
+template <>
+struct Store<kF64> {
+  using T = double;
+  using R = double;
+  __device__ static R h(const T* p, int64_t i, int) { return p[i]; }
+  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static double hd(const T* p, int64_t i, int) { return p[i]; }
+};
+template <>
+struct Store<kF32> {
+  using T = float;
+  using R = float;
+  __device__ static R h(const T* p, int64_t i, int) { return p[i]; }
+  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static double hd(const T* p, int64_t i, int) { return (double)p[i]; }
+};
+template <>
+struct Store<kF16> {
+  using T = __half;
+  using R = float;
+  __device__ static R h(const T* p, int64_t i, int) { return __half2float(p[i]); }
+  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = __float2half_rn(hq); }
+  __device__ static double hd(const T* p, int64_t i, int) { return (double)__half2float(p[i]); }
+};
+
+template <int ST>
+using RealOf = typename Store<ST>::R;
+
+// ------------------------------------------------------------ work items --
+__device__ __forceinline__ int find_sim(const int32_t* off, int nsim, int item) {
+  int lo = 0, hi = nsim;  // off[lo] <= item < off[hi]
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (off[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.
+// Renumber blocks so that the blocks of one XCD take a contiguous range of
+// work items (neighbouring bricks / nodes of one capsule share an L2).
+// Launches round the grid up to a multiple of kXcds.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_block() {
+  const int per = (int)gridDim.x / kXcds;
+  return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+__device__ __forceinline__ int wrap(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// ------------------------------------------------------------ geometry ----
+struct D3 {
+  double x, y, z;
+};
+__device__ __forceinline__ D3 sub(D3 a, D3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ __forceinline__ double dot(D3 a, D3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ __forceinline__ D3 cross(D3 a, D3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+__device__ __forceinline__ D3 scale(D3 a, double s) { return {a.x * s, a.y * s, a.z * s}; }
+
+// Bending angle of edge (v1, v2) between the triangles (v1, v2, v0) and
+// (v2, v1, v3), both counter-clockwise seen from outside: the signed angle
+// between their outward normals nA = e x (v0 - v1), nB = (v3 - v2) x e with
+// e = v2 - v1, positive where the surface is convex.  Returns cos and sin.
+__device__ __forceinline__ void bend_angle(D3 v0, D3 v1, D3 v2, D3 v3, double& c, double& s) {
+  D3 e = sub(v2, v1);
+  D3 nA = cross(e, sub(v0, v1));
+  D3 nB = cross(sub(v3, v2), e);
+  double inv = 1.0 / sqrt(dot(nA, nA) * dot(nB, nB));
+  c = dot(nA, nB) * inv;
+  s = dot(cross(nA, nB), e) * inv / sqrt(dot(e, e));
+}
+
+// Force on the vertex with the given role (0: v0, 1: v1, 2: v2, 3: v3) from the
+// bending energy kb (1 - cos(theta - theta0)) of one edge, Eq. (8):
+// F = -kb sin(theta - theta0) dtheta/dv.  The angle gradient: the wing
+// vertices move their triangle about the edge, dtheta/dv0 = -|e| nA/|nA|^2,
+// dtheta/dv3 = -|e| nB/|nB|^2; the edge vertices take the complementary
+// shares fixed by translation and rotation invariance, weighted by where the
+// wings project onto the edge (t0, t3).
+__device__ __forceinline__ D3 bend_force(D3 v0, D3 v1, D3 v2, D3 v3, double c0, double s0,
+                                         double kb, int role) {
+  D3 e = sub(v2, v1);
+  D3 a = sub(v0, v1);
+  D3 nA = cross(e, a);
+  D3 nB = cross(sub(v3, v2), e);
+  double e2 = dot(e, e), le = sqrt(e2);
+  double nA2 = dot(nA, nA), nB2 = dot(nB, nB);
+  double inv = 1.0 / sqrt(nA2 * nB2);
+  double ct = dot(nA, nB) * inv;
+  double st = dot(cross(nA, nB), e) * inv / le;
+  double dEdth = kb * (st * c0 - ct * s0);  // kb sin(theta - theta0)
+  D3 g0 = scale(nA, -le / nA2);
+  D3 g3 = scale(nB, -le / nB2);
+  double t0 = dot(a, e) / e2;
+  double t3 = dot(sub(v3, v1), e) / e2;
+  double k0, k3;
+  if (role == 0) { k0 = 1.0; k3 = 0.0; }
+  else if (role == 3) { k0 = 0.0; k3 = 1.0; }
+  else if (role == 1) { k0 = t0 - 1.0; k3 = t3 - 1.0; }
+  else { k0 = -t0; k3 = -t3; }
+  return {-dEdth * (k0 * g0.x + k3 * g3.x), -dEdth * (k0 * g0.y + k3 * g3.y),
+          -dEdth * (k0 * g0.z + k3 * g3.z)};
+}
+
+// Four delta weights of one axis for a node at fractional offset d in [0, 1)
+// from its base cell, at stencil offsets -1, 0, +1, +2.
+__device__ __forceinline__ void delta_weights(int kind, double d, double w[4]) {
+  if (kind == kCos) {
+    // 1/4 (1 + cos(pi r / 2)) at r = -1-d, -d, 1-d, 2-d, with t = pi d / 2
+    double s, c;
+    sincos(1.5707963267948966 * d, &s, &c);
+    w[0] = 0.25 * (1.0 - s);
+    w[1] = 0.25 * (1.0 + c);
+    w[2] = 0.25 * (1.0 + s);
+    w[3] = 0.25 * (1.0 - c);
+  } else {
+    // Peskin's 4-point kernel: every offset shares sqrt(1 + 4d - 4d^2)
+    double q = sqrt(fmax(1.0 + 4.0 * d - 4.0 * d * d, 0.0));
+    w[0] = (3.0 - 2.0 * d - q) * 0.125;
+    w[1] = (3.0 - 2.0 * d + q) * 0.125;
+    w[2] = (1.0 + 2.0 * d + q) * 0.125;
+    w[3] = (1.0 + 2.0 * d - q) * 0.125;
+  }
+}
+
+// Forces of one edge's energy 1/2 ks (l - l0)^2 + kb (1 - cos(theta - theta0))
+// on its four vertices: G0 on v0, G3 on v3, F1 on v1; v2 receives
+// -(G0 + G3 + F1) since the edge's forces sum to zero.  Same gradient as
+// bend_force, evaluated once for all four roles.
+__device__ __forceinline__ void edge_forces(D3 v0, D3 v1, D3 v2, D3 v3, double l0, double c0,
+                                            double s0, double ks, double kb, D3& G0, D3& G3,
+                                            D3& F1) {
+  const D3 e = sub(v2, v1);
+  const double e2 = dot(e, e), le = sqrt(e2);
+  F1 = scale(e, ks * (le - l0) / le);  // spring pulls v1 toward v2 when stretched
+  G0 = {0.0, 0.0, 0.0};
+  G3 = {0.0, 0.0, 0.0};
+  if (kb != 0.0) {
+    const D3 a = sub(v0, v1);
+    const D3 nA = cross(e, a);
+    const D3 nB = cross(sub(v3, v2), e);
+    const double nA2 = dot(nA, nA), nB2 = dot(nB, nB);
+    const double inv = 1.0 / sqrt(nA2 * nB2);
+    const double ct = dot(nA, nB) * inv;
+    const double st = dot(cross(nA, nB), e) * inv / le;
+    const double dEdth = kb * (st * c0 - ct * s0);  // kb sin(theta - theta0)
+    G0 = scale(nA, dEdth * le / nA2);
+    G3 = scale(nB, dEdth * le / nB2);
+    const double t0 = dot(a, e) / e2;
+    const double t3 = dot(sub(v3, v1), e) / e2;
+    F1.x += (t0 - 1.0) * G0.x + (t3 - 1.0) * G3.x;
+    F1.y += (t0 - 1.0) * G0.y + (t3 - 1.0) * G3.y;
+    F1.z += (t0 - 1.0) * G0.z + (t3 - 1.0) * G3.z;
+  }
+}
+
+// delta_weights in the precision of the spreading record
+template <typename R>
+__device__ __forceinline__ void delta_weights_r(int kind, R d, R w[4]);
+template <>
+__device__ __forceinline__ void delta_weights_r<double>(int kind, double d, double w[4]) {
+  delta_weights(kind, d, w);
+}
+template <>
+__device__ __forceinline__ void delta_weights_r<float>(int kind, float d, float w[4]) {
+  if (kind == kCos) {
+    float s, c;
+    sincosf(1.5707963267948966f * d, &s, &c);
+    w[0] = 0.25f * (1.0f - s);
+    w[1] = 0.25f * (1.0f + c);
+    w[2] = 0.25f * (1.0f + s);
+    w[3] = 0.25f * (1.0f - c);
+  } else {
+    const float q = sqrtf(fmaxf(1.0f + 4.0f * d - 4.0f * d * d, 0.0f));
+    w[0] = (3.0f - 2.0f * d - q) * 0.125f;
+    w[1] = (3.0f - 2.0f * d + q) * 0.125f;
+    w[2] = (1.0f + 2.0f * d + q) * 0.125f;
+    w[3] = (1.0f + 2.0f * d - q) * 0.125f;
+  }
+}
+
+template <typename R>
+struct alignas(4 * sizeof(R)) R4 {
+  R x, y, z, w;
+};
+
+__device__ __forceinline__ bool solid_cell(const SimDev& S, int x, int y, int z) {
+  return (S.wall[0] && (x == 0 || x == S.n[0] - 1)) || (S.wall[1] && (y == 0 || y == S.n[1] - 1)) ||
+         (S.wall[2] && (z == 0 || z == S.n[2] - 1));
+}
+
+}  // namespace
+}  // namespace ibl

@@ -1,0 +1,555 @@
+// Immersed-boundary kernels of the coupled step (Sec. 2.2-2.3):
+//
+//   k_forces_lds  one workgroup per capsule.  Node positions are staged in
+//                 LDS; every edge's spring + bending forces on its four
+//                 vertices are computed once (FP64) into LDS; each node then
+//                 gathers its incident edge shares in a fixed order.  Writes
+//                 F, the node's spreading record (stencil base, delta weights,
+//                 F) and appends the node to the candidate lists of the 8^3
+//                 bricks its 4x4x4 stencil touches.
+//   k_forces      the same without LDS staging, for templates too large for
+//                 the LDS kernel: every node recomputes its incident edges.
+//   k_spread_fx   FP32 / FP16 storage: one workgroup per brick, Eq. (15) in
+//                 32-bit fixed point in LDS (order-independent integer sums;
+//                 see the kernel's comment).
+//   k_spread      FP64 storage: one workgroup (8 waves) per brick.  Eq. (15) as
+//                 an ordered, atomic-free scatter into the brick's LDS force
+//                 field.  The
+//                 brick's candidates are grouped by which 4-cell block of
+//                 base cells they fall in along each axis (3 x 3 x 3 groups),
+//                 and sorted by (group, node id).  Two groups whose blocks are
+//                 two apart along some axis have disjoint stencils, so the 27
+//                 groups run in 8 phases of mutually disjoint groups, one wave
+//                 per group, each wave applying its nodes in ascending id
+//                 order (lane = stencil point, plain read-add-write).  Every
+//                 cell therefore receives its shares in a fixed order: the
+//                 result is bitwise reproducible and independent of launch
+//                 geometry and batching.
+//   k_interp      Eq. (14): 16 lanes per node (lane = (dx, dy), loop over dz),
+//                 four nodes per lane group in flight, u read as float4 per
+//                 cell, fixed 16-lane reduction tree; X^{n+1} = X^n + U (FP64).
+#include "ibl_device.h"
+
+namespace ibl {
+namespace {
+
+// Spreading record, validity check and candidate-list append of one node.
+template <typename R>
+__device__ void emit_node(const SimDev& S, int gid, const double Xp[3], const double Fv[3]) {
+  const int64_t ms = (int64_t)S.maxn;
+  S.F[gid] = Fv[0];
+  S.F[ms + gid] = Fv[1];
+  S.F[2 * ms + gid] = Fv[2];
+  NodeRec<R> q;
+  int valid = 1;
+  for (int a = 0; a < 3; ++a) {
+    if (!isfinite(Xp[a])) {
+      valid = 0;
+      atomicOr(S.health, (uint32_t)kHNonfiniteX);
+    } else if (S.wall[a] && !(Xp[a] >= 1.0 && Xp[a] < (double)(S.n[a] - 2))) {
+      valid = 0;
+      atomicOr(S.health, (uint32_t)kHNodeRange);
+    }
+  }
+  q.valid = valid;
+  for (int a = 0; a < 3; ++a) {
+    const double fb = valid ? floor(Xp[a]) : 0.0;
+    // periodic axes: the base cell taken modulo n, so consumers wrap with one compare
+    q.base[a] = S.wall[a] ? (int32_t)fb : wrap((int32_t)(fb - (double)S.n[a] * floor(fb / S.n[a])), S.n[a]);
+    R w[4];
+    delta_weights_r<R>(S.delta, (R)(valid ? Xp[a] - fb : 0.0), w);
+    for (int k = 0; k < 4; ++k) q.w[a][k] = w[k];
+    q.F[a] = (R)Fv[a];
+  }
+  q.pad = (R)0;
+  ((NodeRec<R>*)S.rec)[gid] = q;
+  if (!valid) return;
+  int bl[3][4], nbl[3];
+  for (int a = 0; a < 3; ++a) {
+    nbl[a] = 0;
+    for (int k = 0; k < 4; ++k) {
+      int c = q.base[a] - 1 + k;
+      if (!S.wall[a]) c = c < 0 ? c + S.n[a] : (c >= S.n[a] ? c - S.n[a] : c);
+      const int b = c / kBrick;
+      bool dup = false;
+      for (int j = 0; j < nbl[a]; ++j) dup |= (bl[a][j] == b);
+      if (!dup) bl[a][nbl[a]++] = b;
+    }
+  }
+  // usually 1-2 bricks per axis: take all slots first, then store, so the
+  // appends overlap instead of waiting on each other
+  int64_t bid[8];
+  int slot[8];
+  const int nall = nbl[0] * nbl[1] * nbl[2];
+  for (int k0 = 0; k0 < nall; k0 += 8) {
+    const int kn = nall - k0 < 8 ? nall - k0 : 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < kn) {
+        const int kk = k0 + k;
+        const int ix = kk % nbl[0], iy = (kk / nbl[0]) % nbl[1], iz = kk / (nbl[0] * nbl[1]);
+        bid[k] = bl[0][ix] + (int64_t)S.nb[0] * (bl[1][iy] + (int64_t)S.nb[1] * bl[2][iz]);
+        slot[k] = atomicAdd(&S.bcount[bid[k]], 1);
+      }
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (k < kn && slot[k] < kCandCap) S.blist[bid[k] * kCandCap + slot[k]] = gid;
+  }
+}
+
+// Largest |F component| of the workgroup's nodes -> the simulation's max
+// (non-negative floats order like their bit patterns, so an integer max is an
+// exact, order-independent float max).  One atomic per workgroup.
+__device__ void block_fmax(const SimDev& S, float v, uint32_t* red) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  if ((tid & 63) == 0) red[tid >> 6] = __float_as_uint(v);
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t m = 0u;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
+    atomicMax(S.fmax, m);
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ forces (LDS) --
+template <typename R>
+__global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ sims, Items it,
+                                                     int mode) {
+  __shared__ double px[3][kLdsNodes];
+  __shared__ double pe[9][kLdsEdges];
+  __shared__ uint32_t red[16];
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int m = item - it.mesh_off[s];
+    const int tm = S.mesh_tmpl[m];
+    const int off = S.mesh_off[m];
+    const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
+    const int nn = S.t_nn[tm], ne = S.t_ne[tm];
+    const int row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    for (int i = tid; i < nn; i += blockDim.x)
+      for (int a = 0; a < 3; ++a) px[a][i] = S.X[a * ms + off + i];
+    __syncthreads();
+    for (int e = tid; e < ne; e += blockDim.x) {
+      const int* v = S.ev + 4 * (e0 + e);
+      D3 p[4];
+      for (int k = 0; k < 4; ++k) p[k] = {px[0][v[k]], px[1][v[k]], px[2][v[k]]};
+      D3 G0, G3, F1;
+      edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
+      pe[0][e] = G0.x; pe[1][e] = G0.y; pe[2][e] = G0.z;
+      pe[3][e] = G3.x; pe[4][e] = G3.y; pe[5][e] = G3.z;
+      pe[6][e] = F1.x; pe[7][e] = F1.y; pe[8][e] = F1.z;
+    }
+    __syncthreads();
+    float fm = 0.f;
+    for (int i = tid; i < nn; i += blockDim.x) {
+      double F[3] = {0.0, 0.0, 0.0};
+      const int r0 = S.inc_ptr[row0 + i], r1 = S.inc_ptr[row0 + i + 1];
+      // the node's incidence entries, fetched together (a node of a closed
+      // triangulation has 4 x valence entries; 16 covers valence <= 4 in one
+      // batch and larger valences in further batches)
+      for (int rb = r0; rb < r1; rb += 16) {
+      int ents[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) ents[k] = rb + k < r1 ? S.inc[rb + k] : -1;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        if (ents[k] < 0) continue;
+        const int ent = ents[k];
+        const int e = (ent >> 2) - e0, role = ent & 3;
+        for (int a = 0; a < 3; ++a) {
+          double v;
+          if (role == 0) v = pe[a][e];
+          else if (role == 3) v = pe[3 + a][e];
+          else if (role == 1) v = pe[6 + a][e];
+          else v = -(pe[a][e] + pe[3 + a][e] + pe[6 + a][e]);
+          F[a] += v;
+        }
+      }
+      }
+      const double Xp[3] = {px[0][i], px[1][i], px[2][i]};
+      emit_node<R>(S, off + i, Xp, F);
+      fm = fmaxf(fm, (float)fmax(fabs(F[0]), fmax(fabs(F[1]), fabs(F[2]))));
+    }
+    block_fmax(S, isfinite(fm) ? fm : 0.f, red);
+  }
+}
+
+// ----------------------------------------------------- forces (per node) --
+template <typename R>
+__global__ __launch_bounds__(256) void k_forces(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ uint32_t red[4];
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;
+    const int m = item - it.mesh_off[s];
+    const int tm = S.mesh_tmpl[m];
+    const int off = S.mesh_off[m];
+    const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
+    const int nn = S.t_nn[tm];
+    const int row0 = S.t_node0[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const double* X = S.X;
+    float fm = 0.f;
+    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
+      const int gid = off + i;
+      double F[3] = {0.0, 0.0, 0.0};
+      const int r0 = S.inc_ptr[row0 + i], r1 = S.inc_ptr[row0 + i + 1];
+      for (int r = r0; r < r1; ++r) {
+        const int ent = S.inc[r];
+        const int e = ent >> 2, role = ent & 3;
+        const int* v = S.ev + 4 * e;
+        D3 p[4];
+        for (int k = 0; k < 4; ++k) {
+          const int g = off + v[k];
+          p[k] = {X[g], X[ms + g], X[2 * ms + g]};
+        }
+        D3 G0, G3, F1;
+        edge_forces(p[0], p[1], p[2], p[3], S.el0[e], S.ec0[e], S.es0[e], ks, kb, G0, G3, F1);
+        const D3 f = role == 0 ? G0
+                   : role == 3 ? G3
+                   : role == 1 ? F1
+                               : D3{-(G0.x + G3.x + F1.x), -(G0.y + G3.y + F1.y), -(G0.z + G3.z + F1.z)};
+        F[0] += f.x;
+        F[1] += f.y;
+        F[2] += f.z;
+      }
+      const double Xp[3] = {X[gid], X[ms + gid], X[2 * ms + gid]};
+      emit_node<R>(S, gid, Xp, F);
+      fm = fmaxf(fm, (float)fmax(fabs(F[0]), fmax(fabs(F[1]), fabs(F[2]))));
+    }
+    block_fmax(S, isfinite(fm) ? fm : 0.f, red);
+  }
+}
+
+// --------------------------------------------------------------- spread --
+constexpr int kSpreadWaves = 8;
+
+template <typename R>
+__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __restrict__ sims, Items it,
+                                                              int mode) {
+  __shared__ uint32_t key[kCandCap];
+  __shared__ R gl[3][kBrickCells];
+  __shared__ int gbeg[27], gend[27];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
+  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
+    const int s = find_sim(it.brick_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int64_t b = item - it.brick_off[s];
+    const int o[3] = {(int)(b % S.nb[0]) * kBrick, (int)((b / S.nb[0]) % S.nb[1]) * kBrick,
+                      (int)(b / ((int64_t)S.nb[0] * S.nb[1])) * kBrick};
+    // an axis can be split into groups only where the stencil offset from the
+    // brick origin is unambiguous: walls, or periodic axes of >= 16 cells
+    bool split[3];
+    for (int a = 0; a < 3; ++a) split[a] = S.wall[a] || S.n[a] >= 16;
+    int cnt = S.bcount[b];
+    if (tid < 27) gbeg[tid] = gend[tid] = 0;
+    __syncthreads();
+    if (tid == 0) {
+      S.bcount[b] = 0;
+      if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
+    }
+    cnt = cnt > kCandCap ? kCandCap : cnt;
+    int P = 1;
+    while (P < cnt) P <<= 1;
+    const NodeRec<R>* rec = (const NodeRec<R>*)S.rec;
+    for (int i = tid; i < P; i += blockDim.x) {
+      uint32_t k = 0xffffffffu;
+      if (i < cnt) {
+        const int node = S.blist[b * kCandCap + i];
+        int g = 0;
+        for (int a = 2; a >= 0; --a) {
+          int r = rec[node].base[a] - o[a];  // base relative to the brick
+          if (!S.wall[a]) r = r > 8 ? r - S.n[a] : (r < -2 ? r + S.n[a] : r);  // image meeting the brick
+          const int ga = split[a] ? (r + 2) >> 2 : 0;
+          g = 3 * g + ga;
+        }
+        k = ((uint32_t)g << 26) | (uint32_t)node;
+      }
+      key[i] = k;
+    }
+    for (int i = tid; i < kBrickCells; i += blockDim.x) gl[0][i] = gl[1][i] = gl[2][i] = (R)0;
+    __syncthreads();
+    // bitonic sort of key[0..P) ascending: by group, then node id
+    for (int k = 2; k <= P; k <<= 1)
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = tid; i < P; i += blockDim.x) {
+          const int l = i ^ j;
+          if (l > i) {
+            const uint32_t ai = key[i], al = key[l];
+            if ((ai > al) == ((i & k) == 0)) {
+              key[i] = al;
+              key[l] = ai;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const int g = (int)(key[i] >> 26);
+      if (i == 0 || (int)(key[i - 1] >> 26) != g) gbeg[g] = i;
+      if (i == cnt - 1 || (int)(key[i + 1] >> 26) != g) gend[g] = i + 1;
+    }
+    __syncthreads();
+    // 8 phases; in phase (px, py, pz) the groups with (gx, gy, gz) of those
+    // parities run concurrently, one wave each
+    for (int ph = 0; ph < 8; ++ph) {
+      const int p[3] = {ph & 1, (ph >> 1) & 1, ph >> 2};
+      // this wave's group: index wv among the groups of the phase
+      int rem = wv, ga[3];
+      bool have = true;
+      for (int a = 0; a < 3; ++a) {
+        const int choices = p[a] ? 1 : 2;  // parity 0 -> {0, 2}, parity 1 -> {1}
+        ga[a] = p[a] ? 1 : 2 * (rem % choices);
+        rem /= choices;
+      }
+      if (rem > 0) have = false;
+      if (have) {
+        const int g = ga[0] + 3 * (ga[1] + 3 * ga[2]);
+        for (int k = gbeg[g]; k < gend[g]; ++k) {
+          const int node = __builtin_amdgcn_readfirstlane((int)(key[k] & 0x3ffffffu));
+          const NodeRec<R>& q = rec[node];
+          int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy, cz = q.base[2] - 1 + dz;
+          if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
+          if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
+          if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
+          const int lx = cx - o[0], ly = cy - o[1], lz = cz - o[2];
+          if ((unsigned)lx < (unsigned)kBrick && (unsigned)ly < (unsigned)kBrick &&
+              (unsigned)lz < (unsigned)kBrick) {
+            const R w = q.w[0][dx] * q.w[1][dy] * q.w[2][dz];
+            const int li = lx + kBrick * (ly + kBrick * lz);
+            gl[0][li] += w * q.F[0];
+            gl[1][li] += w * q.F[1];
+            gl[2][li] += w * q.F[2];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // shares that landed on solid layers are dropped here
+    R* g = (R*)S.g;
+    for (int i = tid; i < kBrickCells; i += blockDim.x) {
+      const int x = o[0] + (i % kBrick), y = o[1] + (i / kBrick) % kBrick, z = o[2] + i / (kBrick * kBrick);
+      if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
+        const bool sol = solid_cell(S, x, y, z);
+        const int64_t c = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
+        g[c] = sol ? (R)0 : gl[0][i];
+        g[S.ncell + c] = sol ? (R)0 : gl[1][i];
+        g[2 * S.ncell + c] = sol ? (R)0 : gl[2][i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------ spread (fixed point) --
+// FP32 / FP16 storage: Eq. (15) accumulated in 32-bit fixed point in LDS.
+// Every share w F is scaled by 2^s, s = 27 - ceil(log2 max|F|) (the step's
+// largest force component over the whole simulation), rounded to the nearest
+// integer and added with an integer add.  Integer addition is associative, so
+// the per-cell sums are exact and identical whatever order the waves run in:
+// the kernel needs no sorting and no ordering between waves, and its result is
+// bitwise reproducible.  Resolution: max|F| * 2^-27 (below binary32's own
+// rounding of a share); headroom: per-cell |sum| up to 16 max|F|, while the
+// delta kernel's partition of unity bounds it by max|F| times the local number
+// of nodes per cell.
+constexpr int kSpreadFxWaves = 4;
+constexpr int kSpreadStage = 256;  // candidate records staged in LDS per pass
+
+__global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev* __restrict__ sims,
+                                                                  Items it, int mode) {
+  __shared__ int gq[3][kBrickCells];
+  __shared__ NodeRec<float> srec[kSpreadStage];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
+  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
+    const int s = find_sim(it.brick_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int64_t b = item - it.brick_off[s];
+    const int ox = (int)(b % S.nb[0]) * kBrick, oy = (int)((b / S.nb[0]) % S.nb[1]) * kBrick,
+              oz = (int)(b / ((int64_t)S.nb[0] * S.nb[1])) * kBrick;
+    int cnt = S.bcount[b];
+    for (int i = tid; i < kBrickCells; i += blockDim.x) gq[0][i] = gq[1][i] = gq[2][i] = 0;
+    __syncthreads();
+    if (tid == 0) {
+      S.bcount[b] = 0;
+      if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
+    }
+    cnt = cnt > kCandCap ? kCandCap : cnt;
+    int e2;
+    frexpf(__uint_as_float(*S.fmax), &e2);
+    const int sh = 27 - e2;
+    const float sc = ldexpf(1.0f, sh);
+    const NodeRec<float>* rec = (const NodeRec<float>*)S.rec;
+    for (int c0 = 0; c0 < cnt; c0 += kSpreadStage) {
+      const int cn = cnt - c0 < kSpreadStage ? cnt - c0 : kSpreadStage;
+      // stage: one record per thread (independent loads, all in flight together)
+      for (int i = tid; i < cn; i += blockDim.x) srec[i] = rec[S.blist[b * kCandCap + c0 + i]];
+      __syncthreads();
+      for (int k = wv; k < cn; k += kSpreadFxWaves) {
+        const NodeRec<float>& q = srec[k];
+        int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy, cz = q.base[2] - 1 + dz;
+        if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
+        if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
+        if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
+        const int lx = cx - ox, ly = cy - oy, lz = cz - oz;
+        if ((unsigned)lx < (unsigned)kBrick && (unsigned)ly < (unsigned)kBrick &&
+            (unsigned)lz < (unsigned)kBrick) {
+          const float w = q.w[0][dx] * q.w[1][dy] * q.w[2][dz];
+          const int li = lx + kBrick * (ly + kBrick * lz);
+          atomicAdd(&gq[0][li], __float2int_rn(w * (q.F[0] * sc)));
+          atomicAdd(&gq[1][li], __float2int_rn(w * (q.F[1] * sc)));
+          atomicAdd(&gq[2][li], __float2int_rn(w * (q.F[2] * sc)));
+        }
+      }
+      __syncthreads();
+    }
+    const float inv = ldexpf(1.0f, -sh);
+    float* g = (float*)S.g;
+    for (int i = tid; i < kBrickCells; i += blockDim.x) {
+      const int x = ox + (i % kBrick), y = oy + (i / kBrick) % kBrick, z = oz + i / (kBrick * kBrick);
+      if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
+        const bool sol = solid_cell(S, x, y, z);
+        const int64_t c = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
+        g[c] = sol ? 0.f : (float)gq[0][i] * inv;
+        g[S.ncell + c] = sol ? 0.f : (float)gq[1][i] * inv;
+        g[2 * S.ncell + c] = sol ? 0.f : (float)gq[2][i] * inv;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------- interp --
+// Each 16-lane group (lane = (dx, dy), loop over dz) interpolates kInterpChains
+// nodes at once: all their record and velocity loads are issued before any is
+// used, so a workgroup keeps several independent gathers in flight.
+constexpr int kInterpChains = 4;
+static_assert(kNodesPerItem == 16 * kInterpChains, "interpolation work item layout");
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims, Items it, int mode) {
+  const int lane = threadIdx.x & 63;
+  const int grp = threadIdx.x >> 4;  // 16 lane groups per workgroup
+  const int dx = lane & 3, dy = (lane >> 2) & 3;
+  for (int item = xcd_block(); item < it.node_total; item += gridDim.x) {
+    const int s = find_sim(it.node_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;
+    const int node0 = (item - it.node_off[s]) * kNodesPerItem;
+    // the spreading of this step has consumed the force maximum: clear it
+    if (node0 == 0 && threadIdx.x == 0) *S.fmax = 0u;
+    const NodeRec<R>* rec = (const NodeRec<R>*)S.rec;
+    const R4<R>* u4 = (const R4<R>*)S.u;
+    const int64_t plane = (int64_t)S.n[0] * S.n[1];
+    R sx[kInterpChains], sy[kInterpChains], sz[kInterpChains];
+    bool valid[kInterpChains];
+    int64_t cell[kInterpChains][4];
+    R w[kInterpChains][4];
+#pragma unroll
+    for (int j = 0; j < kInterpChains; ++j) {
+      const int node = node0 + j * 16 + grp;
+      valid[j] = false;
+      sx[j] = sy[j] = sz[j] = (R)0;
+      if (node < S.nnodes) {
+        const NodeRec<R>& q = rec[node];
+        valid[j] = q.valid != 0;
+        int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy;
+        if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
+        if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
+        const int64_t row = cx + (int64_t)S.n[0] * cy;
+        const R wxy = q.w[0][dx] * q.w[1][dy];
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz) {
+          int cz = q.base[2] - 1 + dz;
+          if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
+          cell[j][dz] = row + plane * cz;
+          w[j][dz] = wxy * q.w[2][dz];
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kInterpChains; ++j)
+      if (valid[j]) {
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz) {
+          const R4<R> uu = u4[cell[j][dz]];
+          sx[j] += w[j][dz] * uu.x;
+          sy[j] += w[j][dz] * uu.y;
+          sz[j] += w[j][dz] * uu.z;
+        }
+      }
+    // fixed reduction tree over the 16 lanes of each node
+#pragma unroll
+    for (int j = 0; j < kInterpChains; ++j)
+#pragma unroll
+      for (int o = 1; o < 16; o <<= 1) {
+        sx[j] += __shfl_xor(sx[j], o, 16);
+        sy[j] += __shfl_xor(sy[j], o, 16);
+        sz[j] += __shfl_xor(sz[j], o, 16);
+      }
+    if ((lane & 15) == 0) {
+      const int64_t ms = (int64_t)S.maxn;
+#pragma unroll
+      for (int j = 0; j < kInterpChains; ++j) {
+        const int node = node0 + j * 16 + grp;
+        if (node >= S.nnodes) continue;
+        const double U[3] = {valid[j] ? (double)sx[j] : 0.0, valid[j] ? (double)sy[j] : 0.0,
+                             valid[j] ? (double)sz[j] : 0.0};
+        for (int a = 0; a < 3; ++a) S.U[a * ms + node] = U[a];
+        if (mode == 0 && valid[j])
+          for (int a = 0; a < 3; ++a) S.X[a * ms + node] += U[a];
+      }
+    }
+  }
+}
+
+// grid for a grid-stride loop over `items`, a multiple of kXcds (see xcd_block)
+int grid_for(int items, int cap) {
+  const int g = items < cap ? items : cap;
+  return (g + kXcds - 1) / kXcds * kXcds;
+}
+
+template <typename R>
+void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
+  if (it.mesh_total <= 0) return;
+  if (it.big_templates)
+    hipLaunchKernelGGL(k_forces<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(256), 0, s, sims, it, mode);
+  else
+    hipLaunchKernelGGL(k_forces_lds<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(1024), 0, s, sims, it, mode);
+}
+
+}  // namespace
+
+void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
+  if (storage == kF64) forces_impl<double>(sims, it, mode, s);
+  else forces_impl<float>(sims, it, mode, s);
+}
+
+void launch_spread(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
+  if (it.mesh_total <= 0 || it.brick_total <= 0) return;
+  const dim3 grid(grid_for(it.brick_total, 1 << 20));
+  if (storage == kF64) hipLaunchKernelGGL(k_spread<double>, grid, dim3(64 * kSpreadWaves), 0, s, sims, it, mode);
+  else hipLaunchKernelGGL(k_spread_fx, grid, dim3(64 * kSpreadFxWaves), 0, s, sims, it, mode);
+}
+
+void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
+  if (it.node_total <= 0) return;
+  const dim3 grid(grid_for(it.node_total, 1 << 20)), block(256);
+  if (storage == kF64) hipLaunchKernelGGL(k_interp<double>, grid, block, 0, s, sims, it, mode);
+  else hipLaunchKernelGGL(k_interp<float>, grid, block, 0, s, sims, it, mode);
+}
+
+}  // namespace ibl

@@ -11,8 +11,12 @@ constexpr int kQ = 19;
 constexpr int kBrick = 8;            // edge of the cubic bricks used for spreading
 constexpr int kBrickCells = kBrick * kBrick * kBrick;
 constexpr int kCandCap = 2048;       // candidate nodes per brick
-constexpr int kLatticeBlock = 256;   // cells per lattice work item
-constexpr int kNodesPerItem = 4;     // nodes per interpolation work item (one wave each)
+constexpr int kLatticeBlock = 256;   // threads per lattice work item
+constexpr int kLatX = 64;            // lattice work item: 64 cells along x ...
+constexpr int kLatY = 4;             // ... by 4 rows along y
+constexpr int kNodesPerItem = 64;    // nodes per interpolation work item (16 lanes each, 4 chains)
+constexpr int kLdsNodes = 684;       // template size handled by the LDS force kernel
+constexpr int kLdsEdges = 1980;
 constexpr int kReduceItemCells = 4096;
 constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup per mesh)
 
@@ -76,6 +80,7 @@ struct SimDev {
   int32_t* t_nn;          // [max_templates]
   int32_t* t_node0;       // first template-node index
   int32_t* t_edge0;       // first template-edge index
+  int32_t* t_ne;          // edges per template
   int32_t* inc_ptr;       // [max_template_nodes + 1] CSR row pointers over all templates
   int32_t* inc;           // incidence entries: (edge << 2) | role, global edge index
   int32_t* ev;            // [max_template_edges][4] template-local node indices
@@ -86,6 +91,7 @@ struct SimDev {
   int64_t* step;          // completed steps (A/B parity = step & 1)
   int64_t* remaining;     // steps still to run in the current launch sequence
   uint32_t* health;
+  uint32_t* fmax;         // bits of max |F component| over the step's nodes (fixed-point scale)
   double* red;            // [reduce items][4] partial sums
   double* red_out;        // [4] mass, momentum
 };
@@ -94,6 +100,7 @@ struct SimDev {
 struct Items {
   int32_t nsim;
   int32_t lat_total, red_total, mesh_total, brick_total, node_total;
+  int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;
@@ -111,7 +118,12 @@ enum Phase : int {
   kNumPhases = 5
 };
 
-// Kernel launchers (ibl_kernels.hip).  mode: 0 = timestep, 1 = observe.
+// Kernel launchers.  mode: 0 = timestep, 1 = observe.
+// ibl_ib.hip: immersed-boundary phases.
+void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
+void launch_spread(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
+void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
+// ibl_kernels.hip: lattice phases and dispatch.
 hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int init_axis_profile,
                        hipStream_t s);
 hipError_t launch_template_rest(const SimDev* sim, int tmpl, int nedges, const double* xref,

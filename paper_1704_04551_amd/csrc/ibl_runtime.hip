@@ -10,6 +10,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -48,8 +49,8 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
   size_t f0, f1, u, g, rho, X, F, U, rec, bcount, blist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
-  size_t t_nn, t_node0, t_edge0, inc_ptr, inc, ev, el0, ec0, es0;
-  size_t step, remaining, health, red, red_out, simdev, items;
+  size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0;
+  size_t step, remaining, health, fmax, red, red_out, simdev, items;
   size_t total;
   int64_t ncell, nbrick, nred;
 };
@@ -67,8 +68,9 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||
       d->max_template_edges < 0)
     return fail(IBL_ERR_ARG, "negative capacity");
-  const int64_t ncell = (int64_t)d->n[0] * d->n[1] * d->n[2];
-  if (ceil_div(ncell, kLatticeBlock) >= (int64_t)1 << 31) return fail(IBL_ERR_ARG, "lattice too large");
+  if (ceil_div((int64_t)d->n[0] * d->n[1] * d->n[2], kLatticeBlock) >= (int64_t)1 << 31)
+    return fail(IBL_ERR_ARG, "lattice too large");
+  if (d->max_nodes >= (1 << 26)) return fail(IBL_ERR_ARG, "at most 2^26 - 1 nodes per simulation");
   for (int a = 0; a < 3; ++a)
     for (int c = 0; c < 3; ++c)
       if (!isfinite(d->wall_u_lo[a][c]) || !isfinite(d->wall_u_hi[a][c]) || !isfinite(d->g_body[c]))
@@ -95,7 +97,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   };
   L.f0 = take((size_t)kQ * ncell * storage_bytes(st));
   L.f1 = take((size_t)kQ * ncell * storage_bytes(st));
-  L.u = take((size_t)3 * ncell * real_bytes(st));
+  L.u = take((size_t)4 * ncell * real_bytes(st));
   L.g = take((size_t)3 * ncell * real_bytes(st));
   L.rho = take((size_t)ncell * real_bytes(st));
   L.X = take(3 * maxn * 8);
@@ -111,6 +113,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.t_nn = take((size_t)d->max_templates * 4);
   L.t_node0 = take((size_t)d->max_templates * 4);
   L.t_edge0 = take((size_t)d->max_templates * 4);
+  L.t_ne = take((size_t)d->max_templates * 4);
   L.inc_ptr = take(((size_t)d->max_template_nodes + 1) * 4);
   L.inc = take((size_t)d->max_template_edges * 4 * 4);
   L.ev = take((size_t)d->max_template_edges * 4 * 4);
@@ -120,6 +123,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.step = take(8);
   L.remaining = take(8);
   L.health = take(4);
+  L.fmax = take(4);
   L.red = take((size_t)L.nred * 4 * 8);
   L.red_out = take(4 * 8);
   L.simdev = take(sizeof(SimDev));
@@ -145,6 +149,10 @@ struct ibl_sim_s {
   int ntmpl = 0, tnodes = 0, tedges = 0;
   std::vector<int> t_nn, t_node0, t_edge0;
   int inc_total = 0;
+  int big_templates = 0;
+  // per template: internal node i holds the caller's node perm[i] (spatial
+  // order of the reference shape, so neighbouring nodes share cache lines)
+  std::vector<std::vector<int>> t_perm;
   // meshes
   int nmesh = 0, nnodes = 0;
   std::vector<int> mesh_tmpl, mesh_off;
@@ -250,6 +258,7 @@ ibl_status upload_simdev(ibl_sim S) {
   it.mesh_off = S->ditems + 4;
   it.brick_off = S->ditems + 6;
   it.node_off = S->ditems + 8;
+  it.big_templates = S->big_templates;
   drop_graphs(S->g1, S->gN);
   return IBL_OK;
 }
@@ -342,6 +351,7 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.t_nn = (int32_t*)(A + L.t_nn);
   d.t_node0 = (int32_t*)(A + L.t_node0);
   d.t_edge0 = (int32_t*)(A + L.t_edge0);
+  d.t_ne = (int32_t*)(A + L.t_ne);
   d.inc_ptr = (int32_t*)(A + L.inc_ptr);
   d.inc = (int32_t*)(A + L.inc);
   d.ev = (int32_t*)(A + L.ev);
@@ -351,6 +361,7 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.step = (int64_t*)(A + L.step);
   d.remaining = (int64_t*)(A + L.remaining);
   d.health = (uint32_t*)(A + L.health);
+  d.fmax = (uint32_t*)(A + L.fmax);
   d.red = (double*)(A + L.red);
   d.red_out = (double*)(A + L.red_out);
   S->dd = (SimDev*)(A + L.simdev);
@@ -390,11 +401,41 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   if (nn > kMaxTemplateNodes) return fail(IBL_ERR_UNSUPPORTED, "template has too many nodes");
   for (int64_t k = 0; k < 3 * (int64_t)nn; ++k)
     if (!isfinite(xref[k])) return fail(IBL_ERR_ARG, "non-finite reference coordinate");
-  // directed edges: (p -> q) -> opposite vertex of its triangle
+  // internal node order: Morton (Z-order) code of the reference position
+  std::vector<int> perm(nn), inv(nn);
+  {
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int i = 0; i < nn; ++i)
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = fmin(lo[a], xref[3 * i + a]);
+        hi[a] = fmax(hi[a], xref[3 * i + a]);
+      }
+    std::vector<std::pair<uint64_t, int>> key(nn);
+    for (int i = 0; i < nn; ++i) {
+      uint64_t code = 0;
+      uint32_t q[3];
+      for (int a = 0; a < 3; ++a) {
+        const double ext = hi[a] - lo[a];
+        q[a] = ext > 0 ? (uint32_t)fmin(1023.0, (xref[3 * i + a] - lo[a]) / ext * 1023.0) : 0u;
+      }
+      for (int bit = 9; bit >= 0; --bit)
+        for (int a = 0; a < 3; ++a) code = (code << 1) | ((q[a] >> bit) & 1u);
+      key[i] = std::make_pair(code, i);
+    }
+    std::sort(key.begin(), key.end());
+    for (int i = 0; i < nn; ++i) {
+      perm[i] = key[i].second;
+      inv[key[i].second] = i;
+    }
+  }
+  // directed edges (internal numbering): (p -> q) -> opposite vertex of its triangle
   std::map<std::pair<int, int>, int> dir;
   for (int t = 0; t < nt; ++t) {
     for (int k = 0; k < 3; ++k) {
-      const int p = tris[3 * t + k], q = tris[3 * t + (k + 1) % 3], r = tris[3 * t + (k + 2) % 3];
+      const int p0 = tris[3 * t + k], q0 = tris[3 * t + (k + 1) % 3], r0 = tris[3 * t + (k + 2) % 3];
+      if (p0 < 0 || p0 >= nn || q0 < 0 || q0 >= nn || r0 < 0 || r0 >= nn)
+        return fail(IBL_ERR_ARG, "triangle with a bad node index");
+      const int p = inv[p0], q = inv[q0], r = inv[r0];
       if (p < 0 || p >= nn || q < 0 || q >= nn || r < 0 || r >= nn || p == q || q == r || p == r)
         return fail(IBL_ERR_ARG, "triangle with a bad or repeated node index");
       if (!dir.emplace(std::make_pair(p, q), r).second)
@@ -438,14 +479,20 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   if (!e) e = hipMemcpyAsync(d.t_nn + S->ntmpl, &nn, 4, hipMemcpyHostToDevice, S->stream);
   if (!e) e = hipMemcpyAsync(d.t_node0 + S->ntmpl, &n0, 4, hipMemcpyHostToDevice, S->stream);
   if (!e) e = hipMemcpyAsync(d.t_edge0 + S->ntmpl, &e0, 4, hipMemcpyHostToDevice, S->stream);
-  if (!e) e = hipMemcpyAsync(dx, xref, sizeof(double) * 3 * nn, hipMemcpyHostToDevice, S->stream);
+  if (!e) e = hipMemcpyAsync(d.t_ne + S->ntmpl, &ne, 4, hipMemcpyHostToDevice, S->stream);
+  std::vector<double> xr_int(3 * (size_t)nn);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < 3; ++a) xr_int[3 * (size_t)i + a] = xref[3 * (size_t)perm[i] + a];
+  if (!e) e = hipMemcpyAsync(dx, xr_int.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice, S->stream);
   if (!e) e = launch_template_rest(S->dd, S->ntmpl, ne, dx, S->stream);
   if (!e) e = hipStreamSynchronize(S->stream);
   hipFree(dx);
   if (e) return fail(IBL_ERR_DEVICE, std::string("template upload: ") + hipGetErrorString(e));
   S->t_nn.push_back(nn);
+  S->t_perm.push_back(perm);
   S->t_node0.push_back(n0);
   S->t_edge0.push_back(e0);
+  if (nn > kLdsNodes || ne > kLdsEdges) S->big_templates = 1;
   S->tnodes += nn;
   S->tedges += ne;
   S->inc_total += (int)inc.size();
@@ -470,9 +517,10 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
   hipSetDevice(S->device);
   const int off = S->nnodes;
   const size_t ms = (size_t)S->desc.max_nodes;
+  const std::vector<int>& perm = S->t_perm[tmpl];
   std::vector<double> soa(3 * (size_t)nn);
   for (int i = 0; i < nn; ++i)
-    for (int a = 0; a < 3; ++a) soa[(size_t)a * nn + i] = x[3 * i + a];
+    for (int a = 0; a < 3; ++a) soa[(size_t)a * nn + i] = x[3 * (size_t)perm[i] + a];
   SimDev& d = S->hd;
   for (int a = 0; a < 3; ++a) {
     HIPCHK(hipMemcpyAsync(d.X + a * ms + off, soa.data() + (size_t)a * nn, 8 * (size_t)nn,
@@ -540,10 +588,12 @@ ibl_status ibl_read_fields(ibl_sim S, double* rho, double* u, double* g) {
       if (solid(c)) rho[c] = 0.0;
   }
   if (u) {
-    HIPCHK(hipMemcpy(raw.data(), d.u, (size_t)3 * nc * rb, hipMemcpyDeviceToHost));
-    if (dbl) fields_to_host<double>(raw, 3 * nc, u); else fields_to_host<float>(raw, 3 * nc, u);
+    std::vector<char> raw4((size_t)4 * nc * rb);
+    std::vector<double> tmp((size_t)4 * nc);
+    HIPCHK(hipMemcpy(raw4.data(), d.u, (size_t)4 * nc * rb, hipMemcpyDeviceToHost));
+    if (dbl) fields_to_host<double>(raw4, 4 * nc, tmp.data()); else fields_to_host<float>(raw4, 4 * nc, tmp.data());
     for (int64_t c = 0; c < nc; ++c)
-      if (solid(c)) u[c] = u[nc + c] = u[2 * nc + c] = 0.0;
+      for (int a = 0; a < 3; ++a) u[a * nc + c] = solid(c) ? 0.0 : tmp[4 * c + a];
   }
   if (g) {
     HIPCHK(hipMemcpy(raw.data(), d.g, (size_t)3 * nc * rb, hipMemcpyDeviceToHost));
@@ -561,6 +611,7 @@ ibl_status ibl_read_nodes(ibl_sim S, int32_t mesh, double* x, double* u, double*
   if (st) return st;
   const int off = S->mesh_off[mesh];
   const int nn = S->t_nn[S->mesh_tmpl[mesh]];
+  const std::vector<int>& perm = S->t_perm[S->mesh_tmpl[mesh]];
   const size_t ms = (size_t)S->desc.max_nodes;
   std::vector<double> tmp((size_t)nn);
   double* src[3] = {S->hd.X, S->hd.U, S->hd.F};
@@ -569,7 +620,7 @@ ibl_status ibl_read_nodes(ibl_sim S, int32_t mesh, double* x, double* u, double*
     if (!dst[k]) continue;
     for (int a = 0; a < 3; ++a) {
       HIPCHK(hipMemcpy(tmp.data(), src[k] + a * ms + off, 8 * (size_t)nn, hipMemcpyDeviceToHost));
-      for (int i = 0; i < nn; ++i) dst[k][3 * i + a] = tmp[i];
+      for (int i = 0; i < nn; ++i) dst[k][3 * (size_t)perm[i] + a] = tmp[i];
     }
   }
   return IBL_OK;
@@ -750,6 +801,8 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.mesh_off = B->doffs + 2 * (n + 1);
   it.brick_off = B->doffs + 3 * (n + 1);
   it.node_off = B->doffs + 4 * (n + 1);
+  it.big_templates = 0;
+  for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
   *out = B;
   return IBL_OK;
 }

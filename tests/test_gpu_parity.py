@@ -185,6 +185,27 @@ def test_batch_equals_alone():
             assert np.array_equal(a.nodes(m)[0], b.nodes(m)[0])
 
 
+def test_dirty_arena_gives_identical_results():
+    """ibl_sim_create initialises every word the step reads: a simulation built
+    in an arena full of garbage runs bitwise like one in a zeroed arena."""
+    import torch
+    spec = _ragged_spec()
+    runs = []
+    for fill in (0x00, 0xAB, 0xFF):
+        probe = ibl.Sim.from_spec(spec, storage="f32")
+        nbytes = probe.bytes
+        probe.close()
+        arena = torch.full((nbytes,), fill, dtype=torch.uint8, device="cuda")
+        s = ibl.Sim.from_spec(spec, storage="f32", arena=arena)
+        s.step(20)
+        s.sync()
+        runs.append((s.fields()[1], [s.nodes(m)[0] for m in range(3)]))
+    for u, xs in runs[1:]:
+        assert np.array_equal(u, runs[0][0])
+        for a, b in zip(xs, runs[0][1]):
+            assert np.array_equal(a, b)
+
+
 def test_checkpoint_roundtrip_bitwise():
     spec = _ragged_spec()
     ref = ibl.Sim.from_spec(spec, storage="f32")
