@@ -1,5 +1,9 @@
 // Immersed-boundary kernels of the coupled step (Sec. 2.2-2.3):
 //
+//   k_edge_forces / k_node_forces  (templates larger than the LDS kernel
+//                 takes) every edge of every capsule in parallel (FP64 shares
+//                 to scratch), then every node gathers its incident shares in a
+//                 fixed order and writes its record.
 //   k_forces_lds  one workgroup per capsule.  Node positions are staged in
 //                 LDS; every edge's spring + bending forces on its four
 //                 vertices are computed once (FP64) into LDS; each node then
@@ -7,8 +11,6 @@
 //                 F, the node's spreading record (stencil base, delta weights,
 //                 F) and appends the node to the candidate lists of the 8^3
 //                 bricks its 4x4x4 stencil touches.
-//   k_forces      the same without LDS staging, for templates too large for
-//                 the LDS kernel: every node recomputes its incident edges.
 //   k_spread_fx   FP32 / FP16 storage: one workgroup per brick, Eq. (15) in
 //                 32-bit fixed point in LDS (order-independent integer sums;
 //                 see the kernel's comment).
@@ -33,9 +35,12 @@
 namespace ibl {
 namespace {
 
-// Spreading record, validity check and candidate-list append of one node.
+// Spreading record and validity check of one node; returns the bricks its
+// stencil touches (up to 8 of them; more only on periodic axes shorter than
+// 3 bricks, where bin_append adds the rest directly).
 template <typename R>
-__device__ void emit_node(const SimDev& S, int gid, const double Xp[3], const double Fv[3]) {
+__device__ int make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3], int br[8],
+                           int& nbr_total, int bl_out[3][4], int nbl_out[3]) {
   const int64_t ms = (int64_t)S.maxn;
   S.F[gid] = Fv[0];
   S.F[ms + gid] = Fv[1];
@@ -63,55 +68,113 @@ __device__ void emit_node(const SimDev& S, int gid, const double Xp[3], const do
   }
   q.pad = (R)0;
   ((NodeRec<R>*)S.rec)[gid] = q;
-  if (!valid) return;
-  int bl[3][4], nbl[3];
+  nbr_total = 0;
+  if (!valid) return 0;
   for (int a = 0; a < 3; ++a) {
-    nbl[a] = 0;
+    nbl_out[a] = 0;
     for (int k = 0; k < 4; ++k) {
       int c = q.base[a] - 1 + k;
       if (!S.wall[a]) c = c < 0 ? c + S.n[a] : (c >= S.n[a] ? c - S.n[a] : c);
       const int b = c / kBrick;
       bool dup = false;
-      for (int j = 0; j < nbl[a]; ++j) dup |= (bl[a][j] == b);
-      if (!dup) bl[a][nbl[a]++] = b;
+      for (int j = 0; j < nbl_out[a]; ++j) dup |= (bl_out[a][j] == b);
+      if (!dup) bl_out[a][nbl_out[a]++] = b;
     }
   }
-  // usually 1-2 bricks per axis: take all slots first, then store, so the
-  // appends overlap instead of waiting on each other
-  int64_t bid[8];
-  int slot[8];
-  const int nall = nbl[0] * nbl[1] * nbl[2];
-  for (int k0 = 0; k0 < nall; k0 += 8) {
-    const int kn = nall - k0 < 8 ? nall - k0 : 8;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < kn) {
-        const int kk = k0 + k;
-        const int ix = kk % nbl[0], iy = (kk / nbl[0]) % nbl[1], iz = kk / (nbl[0] * nbl[1]);
-        bid[k] = bl[0][ix] + (int64_t)S.nb[0] * (bl[1][iy] + (int64_t)S.nb[1] * bl[2][iz]);
-        slot[k] = atomicAdd(&S.bcount[bid[k]], 1);
-      }
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      if (k < kn && slot[k] < kCandCap) S.blist[bid[k] * kCandCap + slot[k]] = gid;
+  nbr_total = nbl_out[0] * nbl_out[1] * nbl_out[2];
+  const int n8 = nbr_total < 8 ? nbr_total : 8;
+  for (int k = 0; k < n8; ++k) {
+    const int ix = k % nbl_out[0], iy = (k / nbl_out[0]) % nbl_out[1], iz = k / (nbl_out[0] * nbl_out[1]);
+    br[k] = bl_out[0][ix] + S.nb[0] * (bl_out[1][iy] + S.nb[1] * bl_out[2][iz]);
+  }
+  return n8;
+}
+
+// Candidate-list appends of a workgroup, aggregated per brick in LDS: each
+// node takes a rank within its bricks with LDS atomics, then one global add
+// per (workgroup, brick) reserves the range.  Device-scope atomics are the
+// expensive kind on a multi-XCD GPU; this issues one per brick instead of one
+// per (node, brick).  The order of entries in a list is not deterministic;
+// the spreading kernels do not depend on it.
+constexpr int kBinSlots = 512;
+struct BinTable {
+  int key[kBinSlots];
+  int cnt[kBinSlots];
+  int base[kBinSlots];
+  uint32_t mx[kBinSlots];  // largest |F component| appended to the brick (float bits)
+};
+
+__device__ void bin_clear(BinTable& T) {
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x) {
+    T.key[i] = -1;
+    T.cnt[i] = 0;
+    T.mx[i] = 0u;
   }
 }
 
-// Largest |F component| of the workgroup's nodes -> the simulation's max
-// (non-negative floats order like their bit patterns, so an integer max is an
-// exact, order-independent float max).  One atomic per workgroup.
-__device__ void block_fmax(const SimDev& S, float v, uint32_t* red) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  if ((tid & 63) == 0) red[tid >> 6] = __float_as_uint(v);
+__device__ int bin_slot(BinTable& T, int key) {
+  int h = (int)(((uint32_t)key * 2654435761u) >> 23) & (kBinSlots - 1);
+  for (int p = 0; p < 32; ++p) {
+    const int cur = atomicCAS(&T.key[h], -1, key);
+    if (cur == -1 || cur == key) return h;
+    h = (h + 1) & (kBinSlots - 1);
+  }
+  return -1;  // table crowded: the caller appends directly
+}
+
+// All threads of the workgroup call this with their node's bricks (n = 0 for
+// an inactive thread).  Contains barriers: uniform control flow required.
+__device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const int br[8], int nbr_total,
+                           const int bl[3][4], const int nbl[3], uint32_t fbits) {
+  int slot[8], rank[8];
+  bin_clear(T);
   __syncthreads();
-  if (tid == 0) {
-    uint32_t m = 0u;
-    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = red[w] > m ? red[w] : m;
-    atomicMax(S.fmax, m);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    slot[k] = -1;
+    rank[k] = 0;
+    if (k < n) {
+      slot[k] = bin_slot(T, br[k]);
+      if (slot[k] >= 0) {
+        rank[k] = atomicAdd(&T.cnt[slot[k]], 1);
+        atomicMax(&T.mx[slot[k]], fbits);
+      }
+    }
   }
   __syncthreads();
+  for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x)
+    if (T.key[i] >= 0) {
+      T.base[i] = atomicAdd(&S.bcount[T.key[i]], T.cnt[i]);
+      atomicMax(&S.bmax[T.key[i]], T.mx[i]);
+    }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (k < n) {
+      if (slot[k] < 0) atomicMax(&S.bmax[br[k]], fbits);
+      const int pos = slot[k] >= 0 ? T.base[slot[k]] + rank[k] : atomicAdd(&S.bcount[br[k]], 1);
+      if (pos < kCandCap) S.blist[(int64_t)br[k] * kCandCap + pos] = gid;
+    }
+  // bricks beyond the first 8 (tiny periodic domains only)
+  for (int k = 8; k < nbr_total; ++k) {
+    const int ix = k % nbl[0], iy = (k / nbl[0]) % nbl[1], iz = k / (nbl[0] * nbl[1]);
+    const int b = bl[0][ix] + S.nb[0] * (bl[1][iy] + S.nb[1] * bl[2][iz]);
+    atomicMax(&S.bmax[b], fbits);
+    const int pos = atomicAdd(&S.bcount[b], 1);
+    if (pos < kCandCap) S.blist[(int64_t)b * kCandCap + pos] = gid;
+  }
+  __syncthreads();
+}
+
+// Record + aggregated append of one node per thread (active = false: no node).
+template <typename R>
+__device__ void emit_nodes(const SimDev& S, BinTable& T, bool active, int gid, const double Xp[3],
+                           const double Fv[3]) {
+  int br[8], bl[3][4], nbl[3] = {0, 0, 0}, nt = 0, n = 0;
+  if (active) n = make_record<R>(S, gid, Xp, Fv, br, nt, bl, nbl);
+  // largest force component in the precision the spreading reads (float)
+  const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
+  bin_append(S, T, gid, n, br, nt, bl, nbl, __float_as_uint(isfinite(fm) ? fm : 0.f));
 }
 
 // ------------------------------------------------------------ forces (LDS) --
@@ -120,7 +183,7 @@ __global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ 
                                                      int mode) {
   __shared__ double px[3][kLdsNodes];
   __shared__ double pe[9][kLdsEdges];
-  __shared__ uint32_t red[16];
+  __shared__ BinTable bt;
   const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
     const int s = find_sim(it.mesh_off, it.nsim, item);
@@ -147,10 +210,11 @@ __global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ 
       pe[6][e] = F1.x; pe[7][e] = F1.y; pe[8][e] = F1.z;
     }
     __syncthreads();
-    float fm = 0.f;
-    for (int i = tid; i < nn; i += blockDim.x) {
+    for (int i0 = 0; i0 < nn; i0 += blockDim.x) {
+      const int i = i0 + tid;
+      const bool act = i < nn;
       double F[3] = {0.0, 0.0, 0.0};
-      const int r0 = S.inc_ptr[row0 + i], r1 = S.inc_ptr[row0 + i + 1];
+      const int r0 = act ? S.inc_ptr[row0 + i] : 0, r1 = act ? S.inc_ptr[row0 + i + 1] : 0;
       // the node's incidence entries, fetched together (a node of a closed
       // triangulation has 4 x valence entries; 16 covers valence <= 4 in one
       // batch and larger valences in further batches)
@@ -173,59 +237,96 @@ __global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ 
         }
       }
       }
-      const double Xp[3] = {px[0][i], px[1][i], px[2][i]};
-      emit_node<R>(S, off + i, Xp, F);
-      fm = fmaxf(fm, (float)fmax(fabs(F[0]), fmax(fabs(F[1]), fabs(F[2]))));
+      const double Xp[3] = {act ? px[0][i] : 0.0, act ? px[1][i] : 0.0, act ? px[2][i] : 0.0};
+      emit_nodes<R>(S, bt, act, off + i, Xp, F);
     }
-    block_fmax(S, isfinite(fm) ? fm : 0.f, red);
   }
 }
 
-// ----------------------------------------------------- forces (per node) --
-template <typename R>
-__global__ __launch_bounds__(256) void k_forces(const SimDev* __restrict__ sims, Items it, int mode) {
-  __shared__ uint32_t red[4];
-  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
-    const int s = find_sim(it.mesh_off, it.nsim, item);
+// ------------------------------------------------ forces (edge / node split) --
+// k_edge_forces: every edge of every capsule at once -- its spring and bending
+// shares on its four vertices (FP64) go to a scratch slot, 3 * (first node of
+// the capsule) + edge (a closed surface of genus <= 1 has at most 3 edges per
+// node).  k_node_forces: every node gathers the shares of its incident edges
+// in the template's fixed incidence order, then writes its record.
+constexpr int kEdgeChunks = 8;   // workgroups per capsule in the edge kernel
+constexpr int kNodeChunks = 4;   // workgroups per capsule in the node kernel
+
+__global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ sims, Items it, int mode) {
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total * kEdgeChunks; item += gridDim.x) {
+    const int mi = item / kEdgeChunks, c = item % kEdgeChunks;
+    const int s = find_sim(it.mesh_off, it.nsim, mi);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;
-    const int m = item - it.mesh_off[s];
+    const int m = mi - it.mesh_off[s];
     const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
     const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
-    const int nn = S.t_nn[tm];
-    const int row0 = S.t_node0[tm];
+    const int ne = S.t_ne[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
-    const double* X = S.X;
-    float fm = 0.f;
-    for (int i = threadIdx.x; i < nn; i += blockDim.x) {
-      const int gid = off + i;
-      double F[3] = {0.0, 0.0, 0.0};
-      const int r0 = S.inc_ptr[row0 + i], r1 = S.inc_ptr[row0 + i + 1];
-      for (int r = r0; r < r1; ++r) {
-        const int ent = S.inc[r];
-        const int e = ent >> 2, role = ent & 3;
-        const int* v = S.ev + 4 * e;
-        D3 p[4];
-        for (int k = 0; k < 4; ++k) {
-          const int g = off + v[k];
-          p[k] = {X[g], X[ms + g], X[2 * ms + g]};
-        }
-        D3 G0, G3, F1;
-        edge_forces(p[0], p[1], p[2], p[3], S.el0[e], S.ec0[e], S.es0[e], ks, kb, G0, G3, F1);
-        const D3 f = role == 0 ? G0
-                   : role == 3 ? G3
-                   : role == 1 ? F1
-                               : D3{-(G0.x + G3.x + F1.x), -(G0.y + G3.y + F1.y), -(G0.z + G3.z + F1.z)};
-        F[0] += f.x;
-        F[1] += f.y;
-        F[2] += f.z;
+    double* scr = S.escr + 9 * (3 * (int64_t)off);
+    for (int e = c * 256 + tid; e < ne; e += 256 * kEdgeChunks) {
+      const int* v = S.ev + 4 * (e0 + e);
+      D3 p[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int g = off + v[k];
+        p[k] = {S.X[g], S.X[ms + g], S.X[2 * ms + g]};
       }
-      const double Xp[3] = {X[gid], X[ms + gid], X[2 * ms + gid]};
-      emit_node<R>(S, gid, Xp, F);
-      fm = fmaxf(fm, (float)fmax(fabs(F[0]), fmax(fabs(F[1]), fabs(F[2]))));
+      D3 G0, G3, F1;
+      edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
+      double* o = scr + 9 * (int64_t)e;
+      o[0] = G0.x; o[1] = G0.y; o[2] = G0.z;
+      o[3] = G3.x; o[4] = G3.y; o[5] = G3.z;
+      o[6] = F1.x; o[7] = F1.y; o[8] = F1.z;
     }
-    block_fmax(S, isfinite(fm) ? fm : 0.f, red);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ BinTable bt;
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total * kNodeChunks; item += gridDim.x) {
+    const int mi = item / kNodeChunks, c = item % kNodeChunks;
+    const int s = find_sim(it.mesh_off, it.nsim, mi);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int m = mi - it.mesh_off[s];
+    const int tm = S.mesh_tmpl[m];
+    const int off = S.mesh_off[m];
+    const int nn = S.t_nn[tm], row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const double* scr = S.escr + 9 * (3 * (int64_t)off);
+    for (int i0 = c * 256; i0 < nn; i0 += 256 * kNodeChunks) {
+      const int i = i0 + tid;
+      const bool act = i < nn;
+      double F[3] = {0.0, 0.0, 0.0};
+      const int r0 = act ? S.inc_ptr[row0 + i] : 0, r1 = act ? S.inc_ptr[row0 + i + 1] : 0;
+      for (int rb = r0; rb < r1; rb += 16) {
+        int ents[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) ents[k] = rb + k < r1 ? S.inc[rb + k] : -1;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          if (ents[k] < 0) continue;
+          const int role = ents[k] & 3;
+          const double* o = scr + 9 * (int64_t)((ents[k] >> 2) - e0);
+          for (int a = 0; a < 3; ++a) {
+            double v;
+            if (role == 0) v = o[a];
+            else if (role == 3) v = o[3 + a];
+            else if (role == 1) v = o[6 + a];
+            else v = -(o[a] + o[3 + a] + o[6 + a]);
+            F[a] += v;
+          }
+        }
+      }
+      const int gid = off + i;
+      const double Xp[3] = {act ? S.X[gid] : 0.0, act ? S.X[ms + gid] : 0.0, act ? S.X[2 * ms + gid] : 0.0};
+      emit_nodes<R>(S, bt, act, gid, Xp, F);
+    }
   }
 }
 
@@ -257,6 +358,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
     __syncthreads();
     if (tid == 0) {
       S.bcount[b] = 0;
+      S.bmax[b] = 0u;
       if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
     }
     cnt = cnt > kCandCap ? kCandCap : cnt;
@@ -354,8 +456,8 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
 
 // ------------------------------------------------------ spread (fixed point) --
 // FP32 / FP16 storage: Eq. (15) accumulated in 32-bit fixed point in LDS.
-// Every share w F is scaled by 2^s, s = 27 - ceil(log2 max|F|) (the step's
-// largest force component over the whole simulation), rounded to the nearest
+// Every share w F is scaled by 2^s, s = 27 - ceil(log2 max|F|) (the largest
+// force component among the brick's candidate nodes), rounded to the nearest
 // integer and added with an integer add.  Integer addition is associative, so
 // the per-cell sums are exact and identical whatever order the waves run in:
 // the kernel needs no sorting and no ordering between waves, and its result is
@@ -381,18 +483,23 @@ __global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev*
     const int ox = (int)(b % S.nb[0]) * kBrick, oy = (int)((b / S.nb[0]) % S.nb[1]) * kBrick,
               oz = (int)(b / ((int64_t)S.nb[0] * S.nb[1])) * kBrick;
     int cnt = S.bcount[b];
+    // fixed-point scale of this brick: the largest force component among its
+    // candidates, collected (as an order-independent integer max of float
+    // bits) when the nodes were appended
+    const uint32_t fmx = S.bmax[b];
     for (int i = tid; i < kBrickCells; i += blockDim.x) gq[0][i] = gq[1][i] = gq[2][i] = 0;
     __syncthreads();
     if (tid == 0) {
       S.bcount[b] = 0;
+      S.bmax[b] = 0u;
       if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
     }
     cnt = cnt > kCandCap ? kCandCap : cnt;
+    const NodeRec<float>* rec = (const NodeRec<float>*)S.rec;
     int e2;
-    frexpf(__uint_as_float(*S.fmax), &e2);
+    frexpf(__uint_as_float(fmx), &e2);
     const int sh = 27 - e2;
     const float sc = ldexpf(1.0f, sh);
-    const NodeRec<float>* rec = (const NodeRec<float>*)S.rec;
     for (int c0 = 0; c0 < cnt; c0 += kSpreadStage) {
       const int cn = cnt - c0 < kSpreadStage ? cnt - c0 : kSpreadStage;
       // stage: one record per thread (independent loads, all in flight together)
@@ -449,8 +556,6 @@ __global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims,
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;
     const int node0 = (item - it.node_off[s]) * kNodesPerItem;
-    // the spreading of this step has consumed the force maximum: clear it
-    if (node0 == 0 && threadIdx.x == 0) *S.fmax = 0u;
     const NodeRec<R>* rec = (const NodeRec<R>*)S.rec;
     const R4<R>* u4 = (const R4<R>*)S.u;
     const int64_t plane = (int64_t)S.n[0] * S.n[1];
@@ -525,10 +630,14 @@ int grid_for(int items, int cap) {
 template <typename R>
 void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
   if (it.mesh_total <= 0) return;
-  if (it.big_templates)
-    hipLaunchKernelGGL(k_forces<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(256), 0, s, sims, it, mode);
-  else
+  if (it.big_templates || it.forces_variant == 1) {
+    hipLaunchKernelGGL(k_edge_forces, dim3(grid_for(it.mesh_total * kEdgeChunks, 1 << 20)), dim3(256), 0, s,
+                       sims, it, mode);
+    hipLaunchKernelGGL(k_node_forces<R>, dim3(grid_for(it.mesh_total * kNodeChunks, 1 << 20)), dim3(256), 0,
+                       s, sims, it, mode);
+  } else {
     hipLaunchKernelGGL(k_forces_lds<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(1024), 0, s, sims, it, mode);
+  }
 }
 
 }  // namespace

@@ -15,8 +15,8 @@ constexpr int kLatticeBlock = 256;   // threads per lattice work item
 constexpr int kLatX = 64;            // lattice work item: 64 cells along x ...
 constexpr int kLatY = 4;             // ... by 4 rows along y
 constexpr int kNodesPerItem = 64;    // nodes per interpolation work item (16 lanes each, 4 chains)
-constexpr int kLdsNodes = 684;       // template size handled by the LDS force kernel
-constexpr int kLdsEdges = 1980;
+constexpr int kLdsNodes = 642;       // template size handled by the LDS force kernel (icosphere level 3)
+constexpr int kLdsEdges = 1920;
 constexpr int kReduceItemCells = 4096;
 constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup per mesh)
 
@@ -69,7 +69,9 @@ struct SimDev {
   double* F;              // [3][max_nodes] membrane forces
   double* U;              // [3][max_nodes] interpolated velocities
   void* rec;              // [max_nodes] NodeRec
+  double* escr;           // [3 * max_nodes][9] per-edge force shares (G0, G3, F1)
   int32_t* bcount;        // [nbrick]
+  uint32_t* bmax;         // [nbrick] largest |F component| among the brick's candidates (float bits)
   int32_t* blist;         // [nbrick][kCandCap]
   // meshes
   int32_t* mesh_tmpl;     // [max_meshes]
@@ -91,7 +93,6 @@ struct SimDev {
   int64_t* step;          // completed steps (A/B parity = step & 1)
   int64_t* remaining;     // steps still to run in the current launch sequence
   uint32_t* health;
-  uint32_t* fmax;         // bits of max |F component| over the step's nodes (fixed-point scale)
   double* red;            // [reduce items][4] partial sums
   double* red_out;        // [4] mass, momentum
 };
@@ -101,6 +102,7 @@ struct Items {
   int32_t nsim;
   int32_t lat_total, red_total, mesh_total, brick_total, node_total;
   int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
+  int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;

@@ -51,12 +51,14 @@ __global__ __launch_bounds__(kLatticeBlock) void k_init(const SimDev* __restrict
     int x, y, z;
     if (!lat_cell(S, item - it.lat_off[s], threadIdx.x, x, y, z)) continue;
     const int64_t cell = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
-    if (cell < S.nbrick) S.bcount[cell] = 0;
+    if (cell < S.nbrick) {
+      S.bcount[cell] = 0;
+      S.bmax[cell] = 0u;
+    }
     if (cell == 0) {  // every control word: the arena may hold a previous user's data
       *S.step = 0;
       *S.remaining = 0;
       *S.health = 0u;
-      *S.fmax = 0u;
     }
     const int c[3] = {x, y, z};
     R4<R>* u = (R4<R>*)S.u;

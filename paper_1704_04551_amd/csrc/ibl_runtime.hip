@@ -8,6 +8,7 @@
 // are captured once into HIP graphs and replayed; the A/B parity and the
 // remaining-step count live on the device, so a graph is valid at any step.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -38,6 +39,13 @@ ibl_status fail(ibl_status st, const std::string& msg) {
 
 constexpr int kGraphSteps = 16;
 
+// Force-kernel variant (tuning knob; IBL_FORCES=split selects the edge / node
+// split for every template, the default is one LDS workgroup per capsule).
+int forces_variant() {
+  const char* v = getenv("IBL_FORCES");
+  return (v && strcmp(v, "split") == 0) ? 1 : 0;
+}
+
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
 
 int storage_bytes(int st) { return st == kF64 ? 8 : (st == kF32 ? 4 : 2); }
@@ -47,10 +55,10 @@ size_t rec_bytes(int st) { return st == kF64 ? sizeof(NodeRec<double>) : sizeof(
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
-  size_t f0, f1, u, g, rho, X, F, U, rec, bcount, blist;
+  size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, bmax, blist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
   size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0;
-  size_t step, remaining, health, fmax, red, red_out, simdev, items;
+  size_t step, remaining, health, red, red_out, simdev, items;
   size_t total;
   int64_t ncell, nbrick, nred;
 };
@@ -104,7 +112,9 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.F = take(3 * maxn * 8);
   L.U = take(3 * maxn * 8);
   L.rec = take(maxn * rec_bytes(st));
+  L.escr = take(maxn * 3 * 9 * 8);
   L.bcount = take((size_t)nb * 4);
+  L.bmax = take((size_t)nb * 4);
   L.blist = take(ib ? (size_t)nb * kCandCap * 4 : 4);
   L.mesh_tmpl = take((size_t)d->max_meshes * 4);
   L.mesh_off = take((size_t)d->max_meshes * 4);
@@ -123,7 +133,6 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.step = take(8);
   L.remaining = take(8);
   L.health = take(4);
-  L.fmax = take(4);
   L.red = take((size_t)L.nred * 4 * 8);
   L.red_out = take(4 * 8);
   L.simdev = take(sizeof(SimDev));
@@ -259,6 +268,7 @@ ibl_status upload_simdev(ibl_sim S) {
   it.brick_off = S->ditems + 6;
   it.node_off = S->ditems + 8;
   it.big_templates = S->big_templates;
+  it.forces_variant = forces_variant();
   drop_graphs(S->g1, S->gN);
   return IBL_OK;
 }
@@ -342,7 +352,9 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.F = (double*)(A + L.F);
   d.U = (double*)(A + L.U);
   d.rec = A + L.rec;
+  d.escr = (double*)(A + L.escr);
   d.bcount = (int32_t*)(A + L.bcount);
+  d.bmax = (uint32_t*)(A + L.bmax);
   d.blist = (int32_t*)(A + L.blist);
   d.mesh_tmpl = (int32_t*)(A + L.mesh_tmpl);
   d.mesh_off = (int32_t*)(A + L.mesh_off);
@@ -361,7 +373,6 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.step = (int64_t*)(A + L.step);
   d.remaining = (int64_t*)(A + L.remaining);
   d.health = (uint32_t*)(A + L.health);
-  d.fmax = (uint32_t*)(A + L.fmax);
   d.red = (double*)(A + L.red);
   d.red_out = (double*)(A + L.red_out);
   S->dd = (SimDev*)(A + L.simdev);
@@ -455,6 +466,7 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
     }
   }
   const int ne = (int)(ev.size() / 4);
+  if (ne > 3 * nn) return fail(IBL_ERR_UNSUPPORTED, "more than 3 edges per node (surface of genus > 1)");
   if (S->ntmpl + 1 > S->desc.max_templates || S->tnodes + nn > S->desc.max_template_nodes ||
       S->tedges + ne > S->desc.max_template_edges)
     return fail(IBL_ERR_NOMEM, "template capacity exceeded");
@@ -803,6 +815,7 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.node_off = B->doffs + 4 * (n + 1);
   it.big_templates = 0;
   for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
+  it.forces_variant = forces_variant();
   *out = B;
   return IBL_OK;
 }
