@@ -6,6 +6,12 @@
 
 #include "ibl_internal.h"
 
+#if defined(__HIP_DEVICE_COMPILE__)
+#define GLB __attribute__((address_space(1)))
+#else
+#define GLB
+#endif
+
 namespace ibl {
 namespace {
 
@@ -34,25 +40,30 @@ template <>
 struct Store<kF64> {
   using T = double;
   using R = double;
-  __device__ static R h(const T* p, int64_t i, int) { return p[i]; }
-  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static double hd(const T* p, int64_t i, int) { return p[i]; }
+  __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
+  __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static double hd(const GLB T* p, int64_t i, int) { return p[i]; }
 };
 template <>
 struct Store<kF32> {
   using T = float;
   using R = float;
-  __device__ static R h(const T* p, int64_t i, int) { return p[i]; }
-  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static double hd(const T* p, int64_t i, int) { return (double)p[i]; }
+  __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
+  __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)p[i]; }
 };
 template <>
 struct Store<kF16> {
   using T = __half;
   using R = float;
-  __device__ static R h(const T* p, int64_t i, int) { return __half2float(p[i]); }
-  __device__ static void put(T* p, int64_t i, int, R hq) { p[i] = __float2half_rn(hq); }
-  __device__ static double hd(const T* p, int64_t i, int) { return (double)__half2float(p[i]); }
+  // binary16 moved as its 16 bits
+  __device__ static R h(const GLB T* p, int64_t i, int) {
+    return __half2float(__ushort_as_half(((const GLB unsigned short*)p)[i]));
+  }
+  __device__ static void put(GLB T* p, int64_t i, int, R hq) {
+    ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(hq));
+  }
+  __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
 };
 
 template <int ST>

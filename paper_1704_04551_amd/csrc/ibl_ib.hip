@@ -50,10 +50,10 @@ __device__ int make_record(const SimDev& S, int gid, const double Xp[3], const d
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(Xp[a])) {
       valid = 0;
-      atomicOr(S.health, (uint32_t)kHNonfiniteX);
+      atomicOr((unsigned*)S.health, (uint32_t)kHNonfiniteX);
     } else if (S.wall[a] && !(Xp[a] >= 1.0 && Xp[a] < (double)(S.n[a] - 2))) {
       valid = 0;
-      atomicOr(S.health, (uint32_t)kHNodeRange);
+      atomicOr((unsigned*)S.health, (uint32_t)kHNodeRange);
     }
   }
   q.valid = valid;
@@ -67,7 +67,7 @@ __device__ int make_record(const SimDev& S, int gid, const double Xp[3], const d
     q.F[a] = (R)Fv[a];
   }
   q.pad = (R)0;
-  ((NodeRec<R>*)S.rec)[gid] = q;
+  *(NodeRec<R>*)((GLB NodeRec<R>*)S.rec + gid) = q;
   nbr_total = 0;
   if (!valid) return 0;
   for (int a = 0; a < 3; ++a) {
@@ -144,23 +144,23 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const i
   __syncthreads();
   for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x)
     if (T.key[i] >= 0) {
-      T.base[i] = atomicAdd(&S.bcount[T.key[i]], T.cnt[i]);
-      atomicMax(&S.bmax[T.key[i]], T.mx[i]);
+      T.base[i] = atomicAdd((int*)&S.bcount[T.key[i]], T.cnt[i]);
+      atomicMax((unsigned*)&S.bmax[T.key[i]], T.mx[i]);
     }
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if (k < n) {
-      if (slot[k] < 0) atomicMax(&S.bmax[br[k]], fbits);
-      const int pos = slot[k] >= 0 ? T.base[slot[k]] + rank[k] : atomicAdd(&S.bcount[br[k]], 1);
+      if (slot[k] < 0) atomicMax((unsigned*)&S.bmax[br[k]], fbits);
+      const int pos = slot[k] >= 0 ? T.base[slot[k]] + rank[k] : atomicAdd((int*)&S.bcount[br[k]], 1);
       if (pos < kCandCap) S.blist[(int64_t)br[k] * kCandCap + pos] = gid;
     }
   // bricks beyond the first 8 (tiny periodic domains only)
   for (int k = 8; k < nbr_total; ++k) {
     const int ix = k % nbl[0], iy = (k / nbl[0]) % nbl[1], iz = k / (nbl[0] * nbl[1]);
     const int b = bl[0][ix] + S.nb[0] * (bl[1][iy] + S.nb[1] * bl[2][iz]);
-    atomicMax(&S.bmax[b], fbits);
-    const int pos = atomicAdd(&S.bcount[b], 1);
+    atomicMax((unsigned*)&S.bmax[b], fbits);
+    const int pos = atomicAdd((int*)&S.bcount[b], 1);
     if (pos < kCandCap) S.blist[(int64_t)b * kCandCap + pos] = gid;
   }
   __syncthreads();
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ 
       for (int a = 0; a < 3; ++a) px[a][i] = S.X[a * ms + off + i];
     __syncthreads();
     for (int e = tid; e < ne; e += blockDim.x) {
-      const int* v = S.ev + 4 * (e0 + e);
+      const GLB int* v = S.ev + 4 * (e0 + e);
       D3 p[4];
       for (int k = 0; k < 4; ++k) p[k] = {px[0][v[k]], px[1][v[k]], px[2][v[k]]};
       D3 G0, G3, F1;
@@ -265,9 +265,9 @@ __global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ 
     const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
     const int ne = S.t_ne[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
-    double* scr = S.escr + 9 * (3 * (int64_t)off);
+    GLB double* scr = S.escr + 9 * (3 * (int64_t)off);
     for (int e = c * 256 + tid; e < ne; e += 256 * kEdgeChunks) {
-      const int* v = S.ev + 4 * (e0 + e);
+      const GLB int* v = S.ev + 4 * (e0 + e);
       D3 p[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k) {
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ 
       }
       D3 G0, G3, F1;
       edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
-      double* o = scr + 9 * (int64_t)e;
+      GLB double* o = scr + 9 * (int64_t)e;
       o[0] = G0.x; o[1] = G0.y; o[2] = G0.z;
       o[3] = G3.x; o[4] = G3.y; o[5] = G3.z;
       o[6] = F1.x; o[7] = F1.y; o[8] = F1.z;
@@ -298,7 +298,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
     const int off = S.mesh_off[m];
     const int nn = S.t_nn[tm], row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
-    const double* scr = S.escr + 9 * (3 * (int64_t)off);
+    const GLB double* scr = S.escr + 9 * (3 * (int64_t)off);
     for (int i0 = c * 256; i0 < nn; i0 += 256 * kNodeChunks) {
       const int i = i0 + tid;
       const bool act = i < nn;
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
         for (int k = 0; k < 16; ++k) {
           if (ents[k] < 0) continue;
           const int role = ents[k] & 3;
-          const double* o = scr + 9 * (int64_t)((ents[k] >> 2) - e0);
+          const GLB double* o = scr + 9 * (int64_t)((ents[k] >> 2) - e0);
           for (int a = 0; a < 3; ++a) {
             double v;
             if (role == 0) v = o[a];
@@ -359,12 +359,12 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
     if (tid == 0) {
       S.bcount[b] = 0;
       S.bmax[b] = 0u;
-      if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
+      if (cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
     }
     cnt = cnt > kCandCap ? kCandCap : cnt;
     int P = 1;
     while (P < cnt) P <<= 1;
-    const NodeRec<R>* rec = (const NodeRec<R>*)S.rec;
+    const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
     for (int i = tid; i < P; i += blockDim.x) {
       uint32_t k = 0xffffffffu;
       if (i < cnt) {
@@ -420,7 +420,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
         const int g = ga[0] + 3 * (ga[1] + 3 * ga[2]);
         for (int k = gbeg[g]; k < gend[g]; ++k) {
           const int node = __builtin_amdgcn_readfirstlane((int)(key[k] & 0x3ffffffu));
-          const NodeRec<R>& q = rec[node];
+          const NodeRec<R>& q = *(const NodeRec<R>*)(rec + node);
           int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy, cz = q.base[2] - 1 + dz;
           if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
           if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
       __syncthreads();
     }
     // shares that landed on solid layers are dropped here
-    R* g = (R*)S.g;
+    GLB R* g = (GLB R*)S.g;
     for (int i = tid; i < kBrickCells; i += blockDim.x) {
       const int x = o[0] + (i % kBrick), y = o[1] + (i / kBrick) % kBrick, z = o[2] + i / (kBrick * kBrick);
       if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
@@ -492,10 +492,10 @@ __global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev*
     if (tid == 0) {
       S.bcount[b] = 0;
       S.bmax[b] = 0u;
-      if (cnt > kCandCap) atomicOr(S.health, (uint32_t)kHOverflow);
+      if (cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
     }
     cnt = cnt > kCandCap ? kCandCap : cnt;
-    const NodeRec<float>* rec = (const NodeRec<float>*)S.rec;
+    const GLB NodeRec<float>* rec = (const GLB NodeRec<float>*)S.rec;
     int e2;
     frexpf(__uint_as_float(fmx), &e2);
     const int sh = 27 - e2;
@@ -503,7 +503,7 @@ __global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev*
     for (int c0 = 0; c0 < cnt; c0 += kSpreadStage) {
       const int cn = cnt - c0 < kSpreadStage ? cnt - c0 : kSpreadStage;
       // stage: one record per thread (independent loads, all in flight together)
-      for (int i = tid; i < cn; i += blockDim.x) srec[i] = rec[S.blist[b * kCandCap + c0 + i]];
+      for (int i = tid; i < cn; i += blockDim.x) srec[i] = *(const NodeRec<float>*)(rec + S.blist[b * kCandCap + c0 + i]);
       __syncthreads();
       for (int k = wv; k < cn; k += kSpreadFxWaves) {
         const NodeRec<float>& q = srec[k];
@@ -524,7 +524,7 @@ __global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev*
       __syncthreads();
     }
     const float inv = ldexpf(1.0f, -sh);
-    float* g = (float*)S.g;
+    GLB float* g = (GLB float*)S.g;
     for (int i = tid; i < kBrickCells; i += blockDim.x) {
       const int x = ox + (i % kBrick), y = oy + (i / kBrick) % kBrick, z = oz + i / (kBrick * kBrick);
       if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
@@ -556,8 +556,8 @@ __global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims,
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;
     const int node0 = (item - it.node_off[s]) * kNodesPerItem;
-    const NodeRec<R>* rec = (const NodeRec<R>*)S.rec;
-    const R4<R>* u4 = (const R4<R>*)S.u;
+    const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
+    const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
     const int64_t plane = (int64_t)S.n[0] * S.n[1];
     R sx[kInterpChains], sy[kInterpChains], sz[kInterpChains];
     bool valid[kInterpChains];
@@ -569,7 +569,7 @@ __global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims,
       valid[j] = false;
       sx[j] = sy[j] = sz[j] = (R)0;
       if (node < S.nnodes) {
-        const NodeRec<R>& q = rec[node];
+        const NodeRec<R>& q = *(const NodeRec<R>*)(rec + node);
         valid[j] = q.valid != 0;
         int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy;
         if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
@@ -590,7 +590,7 @@ __global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims,
       if (valid[j]) {
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz) {
-          const R4<R> uu = u4[cell[j][dz]];
+          const R4<R> uu = *(const R4<R>*)(u4 + cell[j][dz]);
           sx[j] += w[j][dz] * uu.x;
           sy[j] += w[j][dz] * uu.y;
           sz[j] += w[j][dz] * uu.z;

@@ -5,6 +5,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Pointers inside device descriptors are plain pointers on the host and
+// global-address-space pointers in device code, so loads and stores through
+// them compile to global (not generic / flat) memory instructions.
+// (ibl_runtime.hip, host code only, defines IBL_HOST_LAYOUT to see plain
+// pointers in both of its compilation passes; the layout is the same.)
+#if defined(__HIP_DEVICE_COMPILE__) && !defined(IBL_HOST_LAYOUT)
+#define IBL_G(T) T __attribute__((address_space(1)))*
+#else
+#define IBL_G(T) T*
+#endif
+
 namespace ibl {
 
 constexpr int kQ = 19;
@@ -61,40 +72,40 @@ struct SimDev {
   int32_t nmeshes;
   int32_t maxn;           // SoA stride of the node arrays (capacity)
   // state
-  void* f[2];             // populations, [19][ncell] in storage format
-  void* u;                // [3][ncell] velocity (compute precision)
-  void* g;                // [3][ncell] spread force (compute precision)
-  void* rho;              // [ncell] density (observation only)
-  double* X;              // [3][max_nodes] positions
-  double* F;              // [3][max_nodes] membrane forces
-  double* U;              // [3][max_nodes] interpolated velocities
-  void* rec;              // [max_nodes] NodeRec
-  double* escr;           // [3 * max_nodes][9] per-edge force shares (G0, G3, F1)
-  int32_t* bcount;        // [nbrick]
-  uint32_t* bmax;         // [nbrick] largest |F component| among the brick's candidates (float bits)
-  int32_t* blist;         // [nbrick][kCandCap]
+  IBL_G(void) f[2];             // populations, [19][ncell] in storage format
+  IBL_G(void) u;                // [3][ncell] velocity (compute precision)
+  IBL_G(void) g;                // [3][ncell] spread force (compute precision)
+  IBL_G(void) rho;              // [ncell] density (observation only)
+  IBL_G(double) X;              // [3][max_nodes] positions
+  IBL_G(double) F;              // [3][max_nodes] membrane forces
+  IBL_G(double) U;              // [3][max_nodes] interpolated velocities
+  IBL_G(void) rec;              // [max_nodes] NodeRec
+  IBL_G(double) escr;           // [3 * max_nodes][9] per-edge force shares (G0, G3, F1)
+  IBL_G(int32_t) bcount;        // [nbrick]
+  IBL_G(uint32_t) bmax;         // [nbrick] largest |F component| among the brick's candidates (float bits)
+  IBL_G(int32_t) blist;         // [nbrick][kCandCap]
   // meshes
-  int32_t* mesh_tmpl;     // [max_meshes]
-  int32_t* mesh_off;      // [max_meshes] first global node
-  double* mesh_ks;
-  double* mesh_kb;
+  IBL_G(int32_t) mesh_tmpl;     // [max_meshes]
+  IBL_G(int32_t) mesh_off;      // [max_meshes] first global node
+  IBL_G(double) mesh_ks;
+  IBL_G(double) mesh_kb;
   // templates
-  int32_t* t_nn;          // [max_templates]
-  int32_t* t_node0;       // first template-node index
-  int32_t* t_edge0;       // first template-edge index
-  int32_t* t_ne;          // edges per template
-  int32_t* inc_ptr;       // [max_template_nodes + 1] CSR row pointers over all templates
-  int32_t* inc;           // incidence entries: (edge << 2) | role, global edge index
-  int32_t* ev;            // [max_template_edges][4] template-local node indices
-  double* el0;            // [max_template_edges] rest length
-  double* ec0;            // cos(theta0)
-  double* es0;            // sin(theta0)
+  IBL_G(int32_t) t_nn;          // [max_templates]
+  IBL_G(int32_t) t_node0;       // first template-node index
+  IBL_G(int32_t) t_edge0;       // first template-edge index
+  IBL_G(int32_t) t_ne;          // edges per template
+  IBL_G(int32_t) inc_ptr;       // [max_template_nodes + 1] CSR row pointers over all templates
+  IBL_G(int32_t) inc;           // incidence entries: (edge << 2) | role, global edge index
+  IBL_G(int32_t) ev;            // [max_template_edges][4] template-local node indices
+  IBL_G(double) el0;            // [max_template_edges] rest length
+  IBL_G(double) ec0;            // cos(theta0)
+  IBL_G(double) es0;            // sin(theta0)
   // control
-  int64_t* step;          // completed steps (A/B parity = step & 1)
-  int64_t* remaining;     // steps still to run in the current launch sequence
-  uint32_t* health;
-  double* red;            // [reduce items][4] partial sums
-  double* red_out;        // [4] mass, momentum
+  IBL_G(int64_t) step;          // completed steps (A/B parity = step & 1)
+  IBL_G(int64_t) remaining;     // steps still to run in the current launch sequence
+  IBL_G(uint32_t) health;
+  IBL_G(double) red;            // [reduce items][4] partial sums
+  IBL_G(double) red_out;        // [4] mass, momentum
 };
 
 // Work-item prefix tables of a launch set (one simulation or a batch).

@@ -61,13 +61,13 @@ __global__ __launch_bounds__(kLatticeBlock) void k_init(const SimDev* __restrict
       *S.health = 0u;
     }
     const int c[3] = {x, y, z};
-    R4<R>* u = (R4<R>*)S.u;
-    R* g = (R*)S.g;
-    R* rho = (R*)S.rho;
+    GLB R4<R>* u = (GLB R4<R>*)S.u;
+    GLB R* g = (GLB R*)S.g;
+    GLB R* rho = (GLB R*)S.rho;
     for (int a = 0; a < 3; ++a) g[a * S.ncell + cell] = (R)0;
     rho[cell] = (R)0;
-    T* f0 = (T*)S.f[0];
-    T* f1 = (T*)S.f[1];
+    GLB T* f0 = (GLB T*)S.f[0];
+    GLB T* f1 = (GLB T*)S.f[1];
     // solid layer: hold the velocity of the first wall axis it belongs to
     int sa = -1;
     for (int a = 0; a < 3; ++a)
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kLatticeBlock) void k_init(const SimDev* __restrict
     double u0[3] = {0.0, 0.0, 0.0};
     if (sa >= 0) {
       const double* v = (c[sa] == 0) ? S.ulo[sa] : S.uhi[sa];
-      u[cell] = R4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
+      *(R4<R>*)(u + cell) = R4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
 #pragma unroll
       for (int q = 0; q < kQ; ++q) {
         Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)0);
@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kLatticeBlock) void k_init(const SimDev* __restrict
         for (int a = 0; a < 3; ++a) u0[a] = S.ulo[pa][a] + (S.uhi[pa][a] - S.ulo[pa][a]) * sfrac;
       }
     }
-    u[cell] = R4<R>{(R)u0[0], (R)u0[1], (R)u0[2], (R)0};
+    *(R4<R>*)(u + cell) = R4<R>{(R)u0[0], (R)u0[1], (R)u0[2], (R)0};
     const double usq = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -112,7 +112,7 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nedges) return;
   const int ge = S.t_edge0[tmpl] + e;
-  const int* v = S.ev + 4 * ge;
+  const GLB int* v = S.ev + 4 * ge;
   D3 p[4];
   for (int k = 0; k < 4; ++k) p[k] = {xref[3 * v[k]], xref[3 * v[k] + 1], xref[3 * v[k] + 2]};
   D3 d = sub(p[2], p[1]);
@@ -137,17 +137,17 @@ __global__ __launch_bounds__(kLatticeBlock) void k_lattice(const SimDev* __restr
     if (!lat_cell(S, item - it.lat_off[s], threadIdx.x, x, y, z)) continue;
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     const int64_t cell = x + (int64_t)nx * (y + (int64_t)ny * z);
-    R4<R>* uf = (R4<R>*)S.u;
+    GLB R4<R>* uf = (GLB R4<R>*)S.u;
     const int64_t nc = S.ncell;
     if (solid_cell(S, x, y, z)) {
       if (mode == 1) {
-        R* rf = (R*)S.rho;
+        GLB R* rf = (GLB R*)S.rho;
         rf[cell] = (R)0;
       }
       continue;
     }
     const int par = (int)(*S.step & 1);
-    const T* src = (const T*)S.f[par];
+    const GLB T* src = (const GLB T*)S.f[par];
     R h[kQ];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) h[q] = Store<ST>::h(src, (int64_t)q * nc + cell, q);
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kLatticeBlock) void k_lattice(const SimDev* __restr
     }
     R gx = (R)S.gb[0], gy = (R)S.gb[1], gz = (R)S.gb[2];
     if (S.has_ib) {
-      const R* gf = (const R*)S.g;
+      const GLB R* gf = (const GLB R*)S.g;
       gx += gf[cell];
       gy += gf[nc + cell];
       gz += gf[2 * nc + cell];
@@ -173,18 +173,18 @@ __global__ __launch_bounds__(kLatticeBlock) void k_lattice(const SimDev* __restr
     const R uy = (jy + (R)0.5 * gy) * irho;
     const R uz = (jz + (R)0.5 * gz) * irho;
     if (mode == 1) {
-      R* rf = (R*)S.rho;
+      GLB R* rf = (GLB R*)S.rho;
       rf[cell] = rho;
-      uf[cell] = R4<R>{ux, uy, uz, (R)0};
+      *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
       continue;
     }
-    if (S.has_ib) uf[cell] = R4<R>{ux, uy, uz, (R)0};
+    if (S.has_ib) *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
     // collision, Eq. (1), (2), (4), in offset form h = f - w
     const R om = (R)(1.0 / S.tau);
     const R pre = (R)(1.0 - 0.5 / S.tau);
     const R usq = ux * ux + uy * uy + uz * uz;
     const R ug = ux * gx + uy * gy + uz * gz;
-    T* dst = (T*)S.f[par ^ 1];
+    GLB T* dst = (GLB T*)S.f[par ^ 1];
     const int wx = S.wall[0], wy = S.wall[1], wz = S.wall[2];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
@@ -239,7 +239,7 @@ __global__ __launch_bounds__(256) void k_reduce(const SimDev* __restrict__ sims,
     const SimDev& S = sims[s];
     const int64_t c0 = (int64_t)(item - it.red_off[s]) * kReduceItemCells;
     const int par = (int)(*S.step & 1);
-    const T* f = (const T*)S.f[par];
+    const GLB T* f = (const GLB T*)S.f[par];
     double m = 0.0, px = 0.0, py = 0.0, pz = 0.0;
     uint32_t bad = 0u;
     for (int k = threadIdx.x; k < kReduceItemCells; k += blockDim.x) {
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_reduce(const SimDev* __restrict__ sims,
       py += jy;
       pz += jz;
     }
-    if (bad) atomicOr(S.health, bad);
+    if (bad) atomicOr((unsigned*)S.health, bad);
     sh[0][threadIdx.x] = m;
     sh[1][threadIdx.x] = px;
     sh[2][threadIdx.x] = py;

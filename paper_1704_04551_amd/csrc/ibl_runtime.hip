@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/ibl.h"
+#define IBL_HOST_LAYOUT 1
 #include "ibl_internal.h"
 
 using namespace ibl;
