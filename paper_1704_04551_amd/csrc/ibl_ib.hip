@@ -11,9 +11,9 @@
 //                 F, the node's spreading record (stencil base, delta weights,
 //                 F) and appends the node to the candidate lists of the 8^3
 //                 bricks its 4x4x4 stencil touches.
-//   k_spread_fx   FP32 / FP16 storage: one workgroup per brick, Eq. (15) in
-//                 32-bit fixed point in LDS (order-independent integer sums;
-//                 see the kernel's comment).
+//   k_spread_fx   FP32 / FP16 storage: one workgroup per brick, one lane per
+//                 candidate node, Eq. (15) in 32-bit fixed point in LDS
+//                 (order-independent integer sums; see the kernel's comment).
 //   k_spread      FP64 storage: one workgroup (8 waves) per brick.  Eq. (15) as
 //                 an ordered, atomic-free scatter into the brick's LDS force
 //                 field.  The
@@ -27,9 +27,10 @@
 //                 cell therefore receives its shares in a fixed order: the
 //                 result is bitwise reproducible and independent of launch
 //                 geometry and batching.
-//   k_interp      Eq. (14): 16 lanes per node (lane = (dx, dy), loop over dz),
-//                 four nodes per lane group in flight, u read as float4 per
-//                 cell, fixed 16-lane reduction tree; X^{n+1} = X^n + U (FP64).
+//   k_interp      Eq. (14): one workgroup per brick, the brick's velocity and
+//                 its stencil margin in LDS, one lane per home node, fixed
+//                 summation order; X^{n+1} = X^n + U (FP64).  Clears the
+//                 brick's candidate list.
 #include "ibl_device.h"
 
 namespace ibl {
@@ -69,7 +70,12 @@ __device__ int make_record(const SimDev& S, int gid, const double Xp[3], const d
   q.pad = (R)0;
   *(NodeRec<R>*)((GLB NodeRec<R>*)S.rec + gid) = q;
   nbr_total = 0;
-  if (!valid) return 0;
+  if (!valid) {  // on no candidate list: interpolation never visits it
+    S.U[gid] = 0.0;
+    S.U[ms + gid] = 0.0;
+    S.U[2 * ms + gid] = 0.0;
+    return 0;
+  }
   for (int a = 0; a < 3; ++a) {
     nbl_out[a] = 0;
     for (int k = 0; k < 4; ++k) {
@@ -356,11 +362,7 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
     int cnt = S.bcount[b];
     if (tid < 27) gbeg[tid] = gend[tid] = 0;
     __syncthreads();
-    if (tid == 0) {
-      S.bcount[b] = 0;
-      S.bmax[b] = 0u;
-      if (cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
-    }
+    if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
     cnt = cnt > kCandCap ? kCandCap : cnt;
     int P = 1;
     while (P < cnt) P <<= 1;
@@ -459,80 +461,100 @@ __global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __re
 // Every share w F is scaled by 2^s, s = 27 - ceil(log2 max|F|) (the largest
 // force component among the brick's candidate nodes), rounded to the nearest
 // integer and added with an integer add.  Integer addition is associative, so
-// the per-cell sums are exact and identical whatever order the waves run in:
-// the kernel needs no sorting and no ordering between waves, and its result is
-// bitwise reproducible.  Resolution: max|F| * 2^-27 (below binary32's own
-// rounding of a share); headroom: per-cell |sum| up to 16 max|F|, while the
-// delta kernel's partition of unity bounds it by max|F| times the local number
-// of nodes per cell.
-constexpr int kSpreadFxWaves = 4;
-constexpr int kSpreadStage = 256;  // candidate records staged in LDS per pass
+// the per-cell sums are exact and identical whatever order the lanes and waves
+// run in: the kernel needs no sorting and no ordering between waves, and its
+// result is bitwise reproducible.  Resolution: max|F| * 2^-27 (below
+// binary32's own rounding of a share); headroom: per-cell |sum| up to
+// 16 max|F|, while the delta kernel's partition of unity bounds it by max|F|
+// times the local number of nodes per cell.
+//
+// One lane per candidate node: the node's four stencil cells per axis are
+// mapped into the brick once (periodic images included), giving a per-axis
+// in-brick mask; the lane then walks its 4 x 4 x 4 stencil, skipping points
+// outside the brick.
+constexpr int kSpreadFxThreads = 256;
 
-__global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev* __restrict__ sims,
+__device__ __forceinline__ void axis_cells(int base, int o, int n, int wall, int l[4], int& mask) {
+  mask = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int c = base - 1 + k;
+    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    l[k] = c - o;
+    mask |= ((unsigned)l[k] < (unsigned)kBrick) ? (1 << k) : 0;
+  }
+}
+
+__global__ __launch_bounds__(kSpreadFxThreads) void k_spread_fx(const SimDev* __restrict__ sims,
                                                                   Items it, int mode) {
   __shared__ int gq[3][kBrickCells];
-  __shared__ NodeRec<float> srec[kSpreadStage];
   const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
   for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
     const int s = find_sim(it.brick_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
+    const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
+    const int nb0 = S.nb[0], nb1 = S.nb[1];
     const int64_t b = item - it.brick_off[s];
-    const int ox = (int)(b % S.nb[0]) * kBrick, oy = (int)((b / S.nb[0]) % S.nb[1]) * kBrick,
-              oz = (int)(b / ((int64_t)S.nb[0] * S.nb[1])) * kBrick;
+    const int bx = (int)(b % nb0), byz = (int)(b / nb0);
+    const int ox = bx * kBrick, oy = (byz % nb1) * kBrick, oz = (byz / nb1) * kBrick;
     int cnt = S.bcount[b];
     // fixed-point scale of this brick: the largest force component among its
     // candidates, collected (as an order-independent integer max of float
     // bits) when the nodes were appended
     const uint32_t fmx = S.bmax[b];
     for (int i = tid; i < kBrickCells; i += blockDim.x) gq[0][i] = gq[1][i] = gq[2][i] = 0;
-    __syncthreads();
-    if (tid == 0) {
-      S.bcount[b] = 0;
-      S.bmax[b] = 0u;
-      if (cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
-    }
+    if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
     cnt = cnt > kCandCap ? kCandCap : cnt;
+    __syncthreads();
     const GLB NodeRec<float>* rec = (const GLB NodeRec<float>*)S.rec;
     int e2;
     frexpf(__uint_as_float(fmx), &e2);
     const int sh = 27 - e2;
     const float sc = ldexpf(1.0f, sh);
-    for (int c0 = 0; c0 < cnt; c0 += kSpreadStage) {
-      const int cn = cnt - c0 < kSpreadStage ? cnt - c0 : kSpreadStage;
-      // stage: one record per thread (independent loads, all in flight together)
-      for (int i = tid; i < cn; i += blockDim.x) srec[i] = *(const NodeRec<float>*)(rec + S.blist[b * kCandCap + c0 + i]);
-      __syncthreads();
-      for (int k = wv; k < cn; k += kSpreadFxWaves) {
-        const NodeRec<float>& q = srec[k];
-        int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy, cz = q.base[2] - 1 + dz;
-        if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
-        if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
-        if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
-        const int lx = cx - ox, ly = cy - oy, lz = cz - oz;
-        if ((unsigned)lx < (unsigned)kBrick && (unsigned)ly < (unsigned)kBrick &&
-            (unsigned)lz < (unsigned)kBrick) {
-          const float w = q.w[0][dx] * q.w[1][dy] * q.w[2][dz];
-          const int li = lx + kBrick * (ly + kBrick * lz);
-          atomicAdd(&gq[0][li], __float2int_rn(w * (q.F[0] * sc)));
-          atomicAdd(&gq[1][li], __float2int_rn(w * (q.F[1] * sc)));
-          atomicAdd(&gq[2][li], __float2int_rn(w * (q.F[2] * sc)));
+    const GLB int32_t* list = S.blist + b * kCandCap;
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const NodeRec<float> q = *(const NodeRec<float>*)(rec + list[i]);
+      int lx[4], ly[4], lz[4], mx, my, mz;
+      axis_cells(q.base[0], ox, n0, w0, lx, mx);
+      axis_cells(q.base[1], oy, n1, w1, ly, my);
+      axis_cells(q.base[2], oz, n2, w2, lz, mz);
+      const float fx = q.F[0] * sc, fy = q.F[1] * sc, fz = q.F[2] * sc;
+#pragma unroll
+      for (int dz = 0; dz < 4; ++dz) {
+        if (!((mz >> dz) & 1)) continue;
+#pragma unroll
+        for (int dy = 0; dy < 4; ++dy) {
+          if (!((my >> dy) & 1)) continue;
+          const float wyz = q.w[1][dy] * q.w[2][dz];
+          const float gx = fx * wyz, gy = fy * wyz, gz = fz * wyz;
+          const int row = kBrick * (ly[dy] + kBrick * lz[dz]);
+#pragma unroll
+          for (int dx = 0; dx < 4; ++dx) {
+            if (!((mx >> dx) & 1)) continue;
+            const float wx = q.w[0][dx];
+            const int li = row + lx[dx];
+            atomicAdd(&gq[0][li], __float2int_rn(gx * wx));
+            atomicAdd(&gq[1][li], __float2int_rn(gy * wx));
+            atomicAdd(&gq[2][li], __float2int_rn(gz * wx));
+          }
         }
       }
-      __syncthreads();
     }
+    __syncthreads();
     const float inv = ldexpf(1.0f, -sh);
     GLB float* g = (GLB float*)S.g;
+    const int64_t nc = S.ncell;
     for (int i = tid; i < kBrickCells; i += blockDim.x) {
-      const int x = ox + (i % kBrick), y = oy + (i / kBrick) % kBrick, z = oz + i / (kBrick * kBrick);
-      if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
+      const int x = ox + (i & (kBrick - 1)), y = oy + ((i / kBrick) & (kBrick - 1)),
+                z = oz + i / (kBrick * kBrick);
+      if (x < n0 && y < n1 && z < n2) {
         const bool sol = solid_cell(S, x, y, z);
-        const int64_t c = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
+        const int64_t c = x + (int64_t)n0 * (y + (int64_t)n1 * z);
         g[c] = sol ? 0.f : (float)gq[0][i] * inv;
-        g[S.ncell + c] = sol ? 0.f : (float)gq[1][i] * inv;
-        g[2 * S.ncell + c] = sol ? 0.f : (float)gq[2][i] * inv;
+        g[nc + c] = sol ? 0.f : (float)gq[1][i] * inv;
+        g[2 * nc + c] = sol ? 0.f : (float)gq[2][i] * inv;
       }
     }
     __syncthreads();
@@ -540,83 +562,117 @@ __global__ __launch_bounds__(64 * kSpreadFxWaves) void k_spread_fx(const SimDev*
 }
 
 // --------------------------------------------------------------- interp --
-// Each 16-lane group (lane = (dx, dy), loop over dz) interpolates kInterpChains
-// nodes at once: all their record and velocity loads are issued before any is
-// used, so a workgroup keeps several independent gathers in flight.
-constexpr int kInterpChains = 4;
-static_assert(kNodesPerItem == 16 * kInterpChains, "interpolation work item layout");
+// Eq. (14) per brick.  Every valid node has one home brick, the brick of its
+// base cell, and is on that brick's candidate list.  The workgroup of a brick
+// picks its home nodes off the list, loads the velocity of the brick and of
+// the stencil margin around it (cells o-1 .. o+9 per axis; solid cells hold
+// their wall's velocity) into LDS, and each lane then sums one node's 64
+// stencil points in a fixed order: the result does not depend on the list's
+// order.  X^{n+1} = X^n + U in FP64.  The workgroup also clears the brick's
+// list for the next step's appends.
+constexpr int kTileEdge = kBrick + 3;
+constexpr int kTileCells = kTileEdge * kTileEdge * kTileEdge;
+constexpr int kInterpThreads = 256;
+
+__device__ __forceinline__ int margin_wrap(int c, int n) {
+  c = c < 0 ? c + n : c;
+  c = c >= n ? c - n : c;
+  c = c >= n ? c - n : c;
+  return c >= n ? c - n : c;
+}
 
 template <typename R>
-__global__ __launch_bounds__(256) void k_interp(const SimDev* __restrict__ sims, Items it, int mode) {
-  const int lane = threadIdx.x & 63;
-  const int grp = threadIdx.x >> 4;  // 16 lane groups per workgroup
-  const int dx = lane & 3, dy = (lane >> 2) & 3;
-  for (int item = xcd_block(); item < it.node_total; item += gridDim.x) {
-    const int s = find_sim(it.node_off, it.nsim, item);
+__global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restrict__ sims, Items it,
+                                                           int mode) {
+  __shared__ R4<R> ut[kTileCells];
+  __shared__ int home[kCandCap];
+  __shared__ int nhome;
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
+    const int s = find_sim(it.brick_off, it.nsim, item);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;
-    const int node0 = (item - it.node_off[s]) * kNodesPerItem;
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
+    const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
+    const int nb0 = S.nb[0], nb1 = S.nb[1];
+    const int64_t b = item - it.brick_off[s];
+    const int bx = (int)(b % nb0), byz = (int)(b / nb0);
+    const int ox = bx * kBrick, oy = (byz % nb1) * kBrick, oz = (byz / nb1) * kBrick;
+    int cnt = S.bcount[b];
+    cnt = cnt > kCandCap ? kCandCap : cnt;
+    if (tid == 0) nhome = 0;
+    __syncthreads();
     const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
-    const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
-    const int64_t plane = (int64_t)S.n[0] * S.n[1];
-    R sx[kInterpChains], sy[kInterpChains], sz[kInterpChains];
-    bool valid[kInterpChains];
-    int64_t cell[kInterpChains][4];
-    R w[kInterpChains][4];
+    const GLB int32_t* list = S.blist + b * kCandCap;
+    for (int i = tid; i < cnt; i += blockDim.x) {
+      const int node = list[i];
+      const GLB int32_t* bs = (const GLB int32_t*)(rec + node);
+      const int rx = bs[0] - ox, ry = bs[1] - oy, rz = bs[2] - oz;
+      if ((unsigned)rx < (unsigned)kBrick && (unsigned)ry < (unsigned)kBrick &&
+          (unsigned)rz < (unsigned)kBrick)
+        home[atomicAdd(&nhome, 1)] = node;
+    }
+    __syncthreads();
+    const int nh = nhome;
+    if (nh > 0) {
+      const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
+      for (int t = tid; t < kTileCells; t += blockDim.x) {
+        const int tx = t % kTileEdge, ty = (t / kTileEdge) % kTileEdge, tz = t / (kTileEdge * kTileEdge);
+        // periodic axes wrap: the margin spans -1 .. n + 8, which three
+        // turns bring into range for any axis of >= 4 cells
+        const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
+        const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
+        const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
+        const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
+        R vx = (R)0, vy = (R)0, vz = (R)0;
+        if (in) {
+          const R4<R> v = *(const R4<R>*)(u4 + (cx + (int64_t)n0 * (cy + (int64_t)n1 * cz)));
+          vx = v.x;
+          vy = v.y;
+          vz = v.z;
+        }
+        ut[t].x = vx;
+        ut[t].y = vy;
+        ut[t].z = vz;
+      }
+      __syncthreads();
+      const int64_t ms = (int64_t)S.maxn;
+      for (int j = tid; j < nh; j += blockDim.x) {
+        const int node = home[j];
+        const NodeRec<R> q = *(const NodeRec<R>*)(rec + node);
+        // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
+        const int t0 = (q.base[0] - ox) + kTileEdge * ((q.base[1] - oy) + kTileEdge * (q.base[2] - oz));
+        R sx = (R)0, sy = (R)0, sz = (R)0;
 #pragma unroll
-    for (int j = 0; j < kInterpChains; ++j) {
-      const int node = node0 + j * 16 + grp;
-      valid[j] = false;
-      sx[j] = sy[j] = sz[j] = (R)0;
-      if (node < S.nnodes) {
-        const NodeRec<R>& q = *(const NodeRec<R>*)(rec + node);
-        valid[j] = q.valid != 0;
-        int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy;
-        if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
-        if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
-        const int64_t row = cx + (int64_t)S.n[0] * cy;
-        const R wxy = q.w[0][dx] * q.w[1][dy];
+        for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
-        for (int dz = 0; dz < 4; ++dz) {
-          int cz = q.base[2] - 1 + dz;
-          if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
-          cell[j][dz] = row + plane * cz;
-          w[j][dz] = wxy * q.w[2][dz];
+          for (int dy = 0; dy < 4; ++dy) {
+            const R wyz = q.w[1][dy] * q.w[2][dz];
+            const int trow = t0 + kTileEdge * (dy + kTileEdge * dz);
+#pragma unroll
+            for (int dx = 0; dx < 4; ++dx) {
+              const R w = q.w[0][dx] * wyz;
+              const R4<R> v = ut[trow + dx];
+              sx += w * v.x;
+              sy += w * v.y;
+              sz += w * v.z;
+            }
+          }
+        const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
+        S.U[node] = ux;
+        S.U[ms + node] = uy;
+        S.U[2 * ms + node] = uz;
+        if (mode == 0) {
+          S.X[node] += ux;
+          S.X[ms + node] += uy;
+          S.X[2 * ms + node] += uz;
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < kInterpChains; ++j)
-      if (valid[j]) {
-#pragma unroll
-        for (int dz = 0; dz < 4; ++dz) {
-          const R4<R> uu = *(const R4<R>*)(u4 + cell[j][dz]);
-          sx[j] += w[j][dz] * uu.x;
-          sy[j] += w[j][dz] * uu.y;
-          sz[j] += w[j][dz] * uu.z;
-        }
-      }
-    // fixed reduction tree over the 16 lanes of each node
-#pragma unroll
-    for (int j = 0; j < kInterpChains; ++j)
-#pragma unroll
-      for (int o = 1; o < 16; o <<= 1) {
-        sx[j] += __shfl_xor(sx[j], o, 16);
-        sy[j] += __shfl_xor(sy[j], o, 16);
-        sz[j] += __shfl_xor(sz[j], o, 16);
-      }
-    if ((lane & 15) == 0) {
-      const int64_t ms = (int64_t)S.maxn;
-#pragma unroll
-      for (int j = 0; j < kInterpChains; ++j) {
-        const int node = node0 + j * 16 + grp;
-        if (node >= S.nnodes) continue;
-        const double U[3] = {valid[j] ? (double)sx[j] : 0.0, valid[j] ? (double)sy[j] : 0.0,
-                             valid[j] ? (double)sz[j] : 0.0};
-        for (int a = 0; a < 3; ++a) S.U[a * ms + node] = U[a];
-        if (mode == 0 && valid[j])
-          for (int a = 0; a < 3; ++a) S.X[a * ms + node] += U[a];
-      }
+    __syncthreads();
+    if (tid == 0) {
+      S.bcount[b] = 0;
+      S.bmax[b] = 0u;
     }
   }
 }
@@ -651,12 +707,12 @@ void launch_spread(int storage, const SimDev* sims, const Items& it, int mode, h
   if (it.mesh_total <= 0 || it.brick_total <= 0) return;
   const dim3 grid(grid_for(it.brick_total, 1 << 20));
   if (storage == kF64) hipLaunchKernelGGL(k_spread<double>, grid, dim3(64 * kSpreadWaves), 0, s, sims, it, mode);
-  else hipLaunchKernelGGL(k_spread_fx, grid, dim3(64 * kSpreadFxWaves), 0, s, sims, it, mode);
+  else hipLaunchKernelGGL(k_spread_fx, grid, dim3(kSpreadFxThreads), 0, s, sims, it, mode);
 }
 
 void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
-  if (it.node_total <= 0) return;
-  const dim3 grid(grid_for(it.node_total, 1 << 20)), block(256);
+  if (it.mesh_total <= 0 || it.brick_total <= 0) return;
+  const dim3 grid(grid_for(it.brick_total, 1 << 20)), block(kInterpThreads);
   if (storage == kF64) hipLaunchKernelGGL(k_interp<double>, grid, block, 0, s, sims, it, mode);
   else hipLaunchKernelGGL(k_interp<float>, grid, block, 0, s, sims, it, mode);
 }
