@@ -6,14 +6,24 @@ random sequential insertion of biconcave (Evans-Fung) cells of 642 nodes,
 diameter 16 lu, to 20 % of the fluid volume, ks 0.005, kb 0.001, cosine delta
 kernel, FP32 population storage.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--storage f32|f16|f64]
 
-Prints one JSON line.  `value` is coupled-step MLUPS (all allocated cells x
-steps / wall time of the K timed steps, inputs resident in HBM).  The timed
-steps run phase by phase with a HIP event after each phase on the
-simulation's stream, which gives the dominant kernel's (collide-stream) mean
-duration for the roofline object.  The CPU baseline times the FP64 oracle on
-a few steps of the same workload on the host cores.
+Prints one JSON line.
+
+* ``value``: coupled-step MLUPS = all allocated cells x K / wall time of K
+  steps run the production way (``ibl_step``: replayed HIP graphs), inputs
+  resident in HBM, bracketed by device synchronisation.
+* ``roofline``: the dominant kernel (collide-stream) against HBM peak.  Its
+  mean duration comes from a second run of K steps launched phase by phase
+  with a HIP event after each phase, on the simulation's own stream.
+  Algorithmic bytes per cell update: 2 x 19 x (storage bytes).
+* ``cpu_baseline``: the FP64 oracle timed on a few steps of the same workload
+  on the host cores; the GPU run of the same steps from the same initial
+  state is compared with it (``error_vs_oracle``).
+* ``batched``: 64 uneven simulations in one batched launch sequence against
+  the same simulations run one after another.
+* ``served``: a Poisson stream of Jeffery-orbit jobs through the serving loop
+  (continuous batching): p50/p99 latency and aggregate MLUPS.
 """
 from __future__ import annotations
 
@@ -55,29 +65,115 @@ def load_spec(args):
     return spec
 
 
-def cpu_baseline(spec, steps):
+def cpu_baseline(spec, steps, storage):
+    """The oracle (FP64, OpenMP over the lattice loops) on `steps` steps of the
+    workload, and the GPU's error against it after the same steps."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
-    import oracle
-    from parity_util import oracle_from_spec
+    from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
+    from paper_1704_04551_amd import ibl
     o = oracle_from_spec(spec)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    return {"value": spec.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
+    base = {"value": spec.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
             "sample": "%d FP64 oracle steps of the same %dx%dx%d workload (%d cells, %d nodes), "
                       "%.1f s" % (steps, *spec.n, len(spec.capsules), spec.nodes, dt)}
+    g = ibl.Sim.from_spec(spec, storage=storage)
+    g.step(steps)
+    g.sync()
+    _, ug, _ = g.fields(rho=False, g=False)
+    _, uo, _ = o.observe()
+    umax, ul2 = field_err(ug, uo, fluid_mask(spec))
+    xa, xr = 0.0, 0.0
+    for m, c in enumerate(spec.capsules):
+        a, r = node_err(g.nodes(m)[0], o.nodes(m)[0], c.x)
+        xa, xr = max(xa, a), max(xr, r)
+    g.close()
+    err = {"after_steps": steps, "u_max_rel": umax, "u_l2_rel": ul2, "x_max_abs_lu": xa,
+           "x_max_rel_to_displacement": xr}
+    return base, err
+
+
+def run_batched(storage, steps):
+    """Config of 64 uneven simulations: one batched launch sequence vs the
+    same simulations one after another (the plain form)."""
+    import torch
+    from paper_1704_04551_amd import ibl
+    from paper_1704_04551_amd import workloads as W
+    specs = W.config_batched(steps=steps)
+    cells = sum(s.cells for s in specs)
+    ks = [s.steps for s in specs]
+    sims = [ibl.Sim.from_spec(s, storage=storage) for s in specs]
+    B = ibl.Batch(sims)
+    B.step([1] * len(sims))  # capture the graphs
+    for s in sims:
+        s.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(ks)
+    sims[0].sync()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    plain = [ibl.Sim.from_spec(s, storage=storage) for s in specs]
+    for p in plain:
+        p.step(1)
+        p.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, k in zip(plain, ks):
+        p.step(k)
+        p.sync()
+    torch.cuda.synchronize()
+    tp = time.perf_counter() - t0
+    same = all(np.array_equal(a.nodes(m)[0], b.nodes(m)[0])
+               for a, b, sp in zip(sims, plain, specs) for m in range(len(sp.capsules)))
+    B.close()
+    for s in sims + plain:
+        s.close()
+    return {"sims": len(specs), "cells": cells, "steps_each": steps,
+            "nodes": sum(s.nodes for s in specs),
+            "batched_mlups": round(cells * steps / tb / 1e6, 1),
+            "plain_mlups": round(cells * steps / tp / 1e6, 1),
+            "batched_s": round(tb, 4), "plain_s": round(tp, 4), "bitwise_same": bool(same)}
+
+
+def run_served(storage, seconds, rate, step_scale, seed=1005):
+    """Poisson arrivals of Jeffery-orbit jobs (ellipsoid of 642 nodes, ks
+    0.05, AR 1.5-4, cubic lattice 48-128, shear rate 0.005) through the
+    serving loop.  Job lengths are the workload's 2000-20000 steps scaled by
+    `step_scale`, so the stream fits the window."""
+    import torch
+    from paper_1704_04551_amd import workloads as W
+    from paper_1704_04551_amd.serve import GpuBackend, Server, poisson_jobs
+    lo, hi = max(1, int(2000 * step_scale)), max(1, int(20000 * step_scale))
+    jobs = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, steps=(lo, hi)), seed)
+    free, total = torch.cuda.mem_get_info()
+    pool = int(0.5 * free)
+    srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=64, queue_cap=4096)
+    try:
+        st = srv.run(jobs, time_limit=3 * seconds)
+    finally:
+        srv.close()
+    st.update({"rate_jobs_s": rate, "window_s": seconds, "jobs": len(jobs),
+               "job_steps": [lo, hi], "pool_bytes": pool})
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
-    ap.add_argument("--cpu-steps", type=int, default=4)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the served run")
+    ap.add_argument("--serve-rate", type=float, default=20.0)
+    ap.add_argument("--serve-step-scale", type=float, default=0.1)
     ap.add_argument("--cache", default=os.path.join(ROOT, "gpurun_out", "rbc_channel_spec.npz"))
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
@@ -110,24 +206,20 @@ def main():
     sim.sync()
     _log("warmup done")
 
+    # timed region: K steps the production way (replayed HIP graphs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    phases, total_ms = sim.profile_phases(args.steps)
+    sim.step(args.steps)
+    sim.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    sim.sync()
-    _log("timed %d steps: %.3f s wall, %.3f ms/step by events" % (args.steps, wall, total_ms / args.steps))
+    _log("timed %d steps: %.4f s" % (args.steps, wall))
 
-    # the same number of steps replayed as HIP graphs (no per-phase events)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ext = torch.cuda.ExternalStream(sim.stream_handle)
-    ev0.record(ext)
-    sim.step(args.steps)
-    ev1.record(ext)
+    # the same number of steps phase by phase, HIP events on the sim's stream
+    phases, total_ms = sim.profile_phases(args.steps)
     sim.sync()
-    graph_ms = ev0.elapsed_time(ev1) / args.steps
     mass, mom, health = sim.conservation()
+    _log("phase run: %.4f ms/step; %s" % (total_ms / args.steps, phases))
 
     cells = spec.cells
     ms_per_step = wall * 1e3 / args.steps
@@ -158,13 +250,21 @@ def main():
                      "bytes_per_launch": lat_bytes, "launch_ms": round(lat_ms, 5)},
         "step_roofline_frac": round(cells * 2 * 19 * sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {k: round(v, 5) for k, v in phases.items()},
-        "graph_ms_per_step": round(graph_ms, 4),
-        "graph_mlups": round(cells / (graph_ms * 1e-3) / 1e6, 1),
         "health": health,
     }
+    sim.close()
     if not args.no_cpu:
         _log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
-        result["cpu_baseline"] = cpu_baseline(spec, args.cpu_steps)
+        result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(spec, args.cpu_steps, args.storage)
+    if not args.no_batched:
+        _log("batched: 64 uneven simulations, %d steps" % args.batched_steps)
+        result["batched"] = run_batched(args.storage, args.batched_steps)
+        _log("batched: %s" % result["batched"])
+    if args.serve_seconds > 0:
+        _log("served: %.0f s of arrivals at %.1f jobs/s" % (args.serve_seconds, args.serve_rate))
+        result["served"] = run_served(args.storage, args.serve_seconds, args.serve_rate,
+                                      args.serve_step_scale)
+        _log("served: %s" % result["served"])
     print(json.dumps(result), flush=True)
 
 

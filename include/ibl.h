@@ -189,7 +189,9 @@ ibl_status ibl_profile_phases(ibl_sim sim, int64_t n_steps, double* ms_out);
  * All simulations must share one storage type and the HIP device; the batch
  * runs on the first simulation's stream.  The batch holds a small device
  * table it allocates itself.  Results of every simulation are bitwise those
- * it gets alone. */
+ * it gets alone.  The member simulations must outlive the batch: destroy the
+ * batch before any of them (ibl_batch_destroy waits on the first member's
+ * stream). */
 ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n_sims, ibl_batch* out);
 /* Advance simulation i by steps_per_sim[i] >= 0 steps (uneven allowed). */
 ibl_status ibl_batch_step(ibl_batch batch, const int64_t* steps_per_sim);

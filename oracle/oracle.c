@@ -439,6 +439,7 @@ typedef struct osim {
   double *X, *F, *U;    /* [nnode][3] */
   long step;
   int err;
+  int obs_valid;        /* F, g, rho, u, U hold the observables of the current state */
 } osim;
 
 static double feq(int i, double rho, const double u[3]) {
@@ -503,6 +504,7 @@ int oracle_template_add(osim *S, int nn, int nt, const int *tri, const double *x
   memset(T, 0, sizeof(*T));
   if (tmpl_build(T, nn, nt, tri) != 0) { tmpl_free(T); return -1; }
   tmpl_rest(T, xref);
+  S->obs_valid = 0;
   return S->ntm++;
 }
 
@@ -519,6 +521,7 @@ int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
   memset(S->F + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
   memset(S->U + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
   S->nnode += nn;
+  S->obs_valid = 0;
   return S->nme++;
 }
 
@@ -526,6 +529,7 @@ int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
  * membrane forces F(X^n), spread g^n, moments rho^n, u^n (Eq. (3) with the
  * total force g_body + g^n), interpolated node velocities U^n. */
 static int observe(osim *S) {
+  if (S->obs_valid) return 0;  /* state unchanged since the last evaluation */
   long nc = S->nc;
   memset(S->F, 0, sizeof(double) * 3 * (size_t)S->nnode);
   for (int m = 0; m < S->nme; ++m) {
@@ -551,6 +555,7 @@ static int observe(osim *S) {
     for (int a = 0; a < 3; ++a) S->u[a * nc + id] = (j[a] + 0.5 * (S->gb[a] + S->g[a * nc + id])) / rho;
   }
   if (interp(&S->G, S->kind, S->nnode, S->X, S->u, S->U) != 0) return -1;
+  S->obs_valid = 1;
   return 0;
 }
 
@@ -561,6 +566,7 @@ static int step1(osim *S) {
   const int *n = S->G.n;
   /* node update X^{n+1} = X^n + U^n (unit time step) */
   for (long k = 0; k < 3L * S->nnode; ++k) S->X[k] += S->U[k];
+  S->obs_valid = 0;
   double om = 1.0 / S->tau, pre = 1.0 - 0.5 / S->tau;
 #pragma omp parallel for schedule(static)
   for (int z = 0; z < n[2]; ++z)
@@ -596,6 +602,7 @@ static int step1(osim *S) {
       }
   double *t = S->f; S->f = S->fn; S->fn = t;
   S->step++;
+  S->obs_valid = 0;
   return 0;
 }
 

@@ -58,7 +58,7 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
   size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, bmax, blist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
-  size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0;
+  size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0, txref;
   size_t step, remaining, health, red, red_out, simdev, items;
   size_t total;
   int64_t ncell, nbrick, nred;
@@ -131,6 +131,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.el0 = take((size_t)d->max_template_edges * 8);
   L.ec0 = take((size_t)d->max_template_edges * 8);
   L.es0 = take((size_t)d->max_template_edges * 8);
+  L.txref = take((size_t)d->max_template_nodes * 3 * 8);  // staging of a template's reference shape
   L.step = take(8);
   L.remaining = take(8);
   L.health = take(4);
@@ -484,8 +485,9 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
     ptr[i + 1] = S->inc_total + (int)inc.size();
   }
   SimDev& d = S->hd;
-  double* dx = nullptr;
-  HIPCHK(hipMalloc(&dx, sizeof(double) * 3 * nn));
+  // the reference shape is staged in the arena (no allocation, so adding a
+  // template does not synchronise the device)
+  double* dx = (double*)(S->arena + S->L.txref) + 3 * (size_t)n0;
   hipError_t e = hipMemcpyAsync(d.ev + 4 * (size_t)e0, ev.data(), ev.size() * 4, hipMemcpyHostToDevice, S->stream);
   if (!e) e = hipMemcpyAsync(d.inc + S->inc_total, inc.data(), inc.size() * 4, hipMemcpyHostToDevice, S->stream);
   if (!e) e = hipMemcpyAsync(d.inc_ptr + n0, ptr.data(), ptr.size() * 4, hipMemcpyHostToDevice, S->stream);
@@ -499,7 +501,6 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   if (!e) e = hipMemcpyAsync(dx, xr_int.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice, S->stream);
   if (!e) e = launch_template_rest(S->dd, S->ntmpl, ne, dx, S->stream);
   if (!e) e = hipStreamSynchronize(S->stream);
-  hipFree(dx);
   if (e) return fail(IBL_ERR_DEVICE, std::string("template upload: ") + hipGetErrorString(e));
   S->t_nn.push_back(nn);
   S->t_perm.push_back(perm);
