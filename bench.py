@@ -42,6 +42,26 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
+def lattice_traffic(storage):
+    """Counter-measured HBM bytes of one collide-stream launch, from the
+    committed profiler summary of this workload, if the kernel sources are
+    still the ones it was measured on (else None)."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "profiles", "k_lattice_rbc_channel_256x128x128_%s_traffic.md" % storage)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m_b = re.search(r"^traffic_bytes_k_lattice: (\d+)$", text, re.M)
+    m_h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
+    if not (m_b and m_h):
+        return None
+    csrc = os.path.join(ROOT, "paper_1704_04551_amd", "csrc")
+    src = b"".join(open(os.path.join(csrc, f), "rb").read()
+                   for f in ("ibl_kernels.hip", "ibl_device.h", "ibl_internal.h"))
+    return int(m_b.group(1)) if hashlib.sha256(src).hexdigest() == m_h.group(1) else None
+
+
 def _log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
@@ -246,7 +266,8 @@ def main():
                    "storage": args.storage, "delta": spec.delta},
         "roofline": {"bound": "hbm", "kernel": "k_lattice (collide-stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": lattice_traffic(args.storage),
                      "bytes_per_launch": lat_bytes, "launch_ms": round(lat_ms, 5)},
         "step_roofline_frac": round(cells * 2 * 19 * sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {k: round(v, 5) for k, v in phases.items()},
