@@ -36,18 +36,39 @@
 namespace ibl {
 namespace {
 
-// Spreading record and validity check of one node; returns the bricks its
-// stencil touches (up to 8 of them; more only on periodic axes shorter than
-// 3 bricks, where bin_append adds the rest directly).
+// The bricks a node's stencil touches.  Along an axis the four stencil cells
+// are consecutive (modulo n), so they meet one or two bricks, a third only
+// on a periodic axis whose last brick is one or two cells wide.  Combination
+// k = ix + 2 iy + 4 iz takes the first (0) or second (1) brick of each axis.
+struct NodeBricks {
+  int br[8];
+  int mask;     // bit k: combination k exists
+  int rare;     // an axis meets a third brick: the node is appended directly
+  int base[3];  // the stencil base cell (periodic axes wrapped)
+};
+
+// brick index along one axis of the four stencil cells from `base`
+__device__ __forceinline__ void axis_bricks(int base, int n, int wall, int b[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int c = base - 1 + k;
+    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    b[k] = c / kBrick;
+  }
+}
+
+// Spreading record and validity check of one node; fills the bricks its
+// stencil touches.
 template <typename R>
-__device__ int make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3], int br[8],
-                           int& nbr_total, int bl_out[3][4], int nbl_out[3]) {
+__device__ void make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3],
+                            NodeBricks& nb) {
   const int64_t ms = (int64_t)S.maxn;
   S.F[gid] = Fv[0];
   S.F[ms + gid] = Fv[1];
   S.F[2 * ms + gid] = Fv[2];
   NodeRec<R> q;
   int valid = 1;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(Xp[a])) {
       valid = 0;
@@ -58,42 +79,49 @@ __device__ int make_record(const SimDev& S, int gid, const double Xp[3], const d
     }
   }
   q.valid = valid;
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double fb = valid ? floor(Xp[a]) : 0.0;
     // periodic axes: the base cell taken modulo n, so consumers wrap with one compare
     q.base[a] = S.wall[a] ? (int32_t)fb : wrap((int32_t)(fb - (double)S.n[a] * floor(fb / S.n[a])), S.n[a]);
     R w[4];
     delta_weights_r<R>(S.delta, (R)(valid ? Xp[a] - fb : 0.0), w);
+#pragma unroll
     for (int k = 0; k < 4; ++k) q.w[a][k] = w[k];
     q.F[a] = (R)Fv[a];
   }
   q.pad = (R)0;
   *(NodeRec<R>*)((GLB NodeRec<R>*)S.rec + gid) = q;
-  nbr_total = 0;
+  nb.mask = 0;
+  nb.rare = 0;
+  nb.base[0] = q.base[0];
+  nb.base[1] = q.base[1];
+  nb.base[2] = q.base[2];
   if (!valid) {  // on no candidate list: interpolation never visits it
     S.U[gid] = 0.0;
     S.U[ms + gid] = 0.0;
     S.U[2 * ms + gid] = 0.0;
-    return 0;
+    return;
   }
+  int p0[3], p1[3], h1[3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
-    nbl_out[a] = 0;
-    for (int k = 0; k < 4; ++k) {
-      int c = q.base[a] - 1 + k;
-      if (!S.wall[a]) c = c < 0 ? c + S.n[a] : (c >= S.n[a] ? c - S.n[a] : c);
-      const int b = c / kBrick;
-      bool dup = false;
-      for (int j = 0; j < nbl_out[a]; ++j) dup |= (bl_out[a][j] == b);
-      if (!dup) bl_out[a][nbl_out[a]++] = b;
-    }
+    int b[4];
+    axis_bricks(q.base[a], S.n[a], S.wall[a], b);
+    p0[a] = b[0];
+    p1[a] = b[1] != b[0] ? b[1] : (b[2] != b[0] ? b[2] : b[3]);
+    h1[a] = p1[a] != b[0];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) nb.rare |= (b[k] != p0[a] && b[k] != p1[a]);
   }
-  nbr_total = nbl_out[0] * nbl_out[1] * nbl_out[2];
-  const int n8 = nbr_total < 8 ? nbr_total : 8;
-  for (int k = 0; k < n8; ++k) {
-    const int ix = k % nbl_out[0], iy = (k / nbl_out[0]) % nbl_out[1], iz = k / (nbl_out[0] * nbl_out[1]);
-    br[k] = bl_out[0][ix] + S.nb[0] * (bl_out[1][iy] + S.nb[1] * bl_out[2][iz]);
+  if (nb.rare) return;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int ix = k & 1, iy = (k >> 1) & 1, iz = k >> 2;
+    const bool ok = (!ix || h1[0]) && (!iy || h1[1]) && (!iz || h1[2]);
+    nb.br[k] = (ix ? p1[0] : p0[0]) + S.nb[0] * ((iy ? p1[1] : p0[1]) + S.nb[1] * (iz ? p1[2] : p0[2]));
+    nb.mask |= ok ? (1 << k) : 0;
   }
-  return n8;
 }
 
 // Candidate-list appends of a workgroup, aggregated per brick in LDS: each
@@ -128,10 +156,15 @@ __device__ int bin_slot(BinTable& T, int key) {
   return -1;  // table crowded: the caller appends directly
 }
 
-// All threads of the workgroup call this with their node's bricks (n = 0 for
+__device__ __forceinline__ void append_one(const SimDev& S, int b, int gid, uint32_t fbits) {
+  atomicMax((unsigned*)&S.bmax[b], fbits);
+  const int pos = atomicAdd((int*)&S.bcount[b], 1);
+  if (pos < kCandCap) S.blist[(int64_t)b * kCandCap + pos] = gid;
+}
+
+// All threads of the workgroup call this with their node's bricks (mask 0 for
 // an inactive thread).  Contains barriers: uniform control flow required.
-__device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const int br[8], int nbr_total,
-                           const int bl[3][4], const int nbl[3], uint32_t fbits) {
+__device__ void bin_append(const SimDev& S, BinTable& T, int gid, const NodeBricks& nb, uint32_t fbits) {
   int slot[8], rank[8];
   bin_clear(T);
   __syncthreads();
@@ -139,8 +172,8 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const i
   for (int k = 0; k < 8; ++k) {
     slot[k] = -1;
     rank[k] = 0;
-    if (k < n) {
-      slot[k] = bin_slot(T, br[k]);
+    if ((nb.mask >> k) & 1) {
+      slot[k] = bin_slot(T, nb.br[k]);
       if (slot[k] >= 0) {
         rank[k] = atomicAdd(&T.cnt[slot[k]], 1);
         atomicMax(&T.mx[slot[k]], fbits);
@@ -156,19 +189,14 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const i
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k)
-    if (k < n) {
-      if (slot[k] < 0) atomicMax((unsigned*)&S.bmax[br[k]], fbits);
-      const int pos = slot[k] >= 0 ? T.base[slot[k]] + rank[k] : atomicAdd((int*)&S.bcount[br[k]], 1);
-      if (pos < kCandCap) S.blist[(int64_t)br[k] * kCandCap + pos] = gid;
+    if ((nb.mask >> k) & 1) {
+      if (slot[k] < 0) {
+        append_one(S, nb.br[k], gid, fbits);
+      } else {
+        const int pos = T.base[slot[k]] + rank[k];
+        if (pos < kCandCap) S.blist[(int64_t)nb.br[k] * kCandCap + pos] = gid;
+      }
     }
-  // bricks beyond the first 8 (tiny periodic domains only)
-  for (int k = 8; k < nbr_total; ++k) {
-    const int ix = k % nbl[0], iy = (k / nbl[0]) % nbl[1], iz = k / (nbl[0] * nbl[1]);
-    const int b = bl[0][ix] + S.nb[0] * (bl[1][iy] + S.nb[1] * bl[2][iz]);
-    atomicMax((unsigned*)&S.bmax[b], fbits);
-    const int pos = atomicAdd((int*)&S.bcount[b], 1);
-    if (pos < kCandCap) S.blist[(int64_t)b * kCandCap + pos] = gid;
-  }
   __syncthreads();
 }
 
@@ -176,21 +204,82 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, int n, const i
 template <typename R>
 __device__ void emit_nodes(const SimDev& S, BinTable& T, bool active, int gid, const double Xp[3],
                            const double Fv[3]) {
-  int br[8], bl[3][4], nbl[3] = {0, 0, 0}, nt = 0, n = 0;
-  if (active) n = make_record<R>(S, gid, Xp, Fv, br, nt, bl, nbl);
+  NodeBricks nb;
+  nb.mask = 0;
+  nb.rare = 0;
+  if (active) make_record<R>(S, gid, Xp, Fv, nb);
   // largest force component in the precision the spreading reads (float)
   const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
-  bin_append(S, T, gid, n, br, nt, bl, nbl, __float_as_uint(isfinite(fm) ? fm : 0.f));
+  const uint32_t fbits = __float_as_uint(isfinite(fm) ? fm : 0.f);
+  if (nb.rare) {
+    // every distinct brick: the stencil points first of their brick per axis
+    int bx[4], by[4], bz[4];
+    axis_bricks(nb.base[0], S.n[0], S.wall[0], bx);
+    axis_bricks(nb.base[1], S.n[1], S.wall[1], by);
+    axis_bricks(nb.base[2], S.n[2], S.wall[2], bz);
+    for (int kz = 0; kz < 4; ++kz) {
+      bool fz = true;
+      for (int j = 0; j < kz; ++j) fz &= bz[j] != bz[kz];
+      for (int ky = 0; ky < 4; ++ky) {
+        bool fy = true;
+        for (int j = 0; j < ky; ++j) fy &= by[j] != by[ky];
+        for (int kx = 0; kx < 4; ++kx) {
+          bool fx = true;
+          for (int j = 0; j < kx; ++j) fx &= bx[j] != bx[kx];
+          if (fx && fy && fz) append_one(S, bx[kx] + S.nb[0] * (by[ky] + S.nb[1] * bz[kz]), gid, fbits);
+        }
+      }
+    }
+  }
+  bin_append(S, T, gid, nb, fbits);
 }
 
 // ------------------------------------------------------------ forces (LDS) --
+// Per-edge force shares are computed in FP64 and kept in LDS in the
+// precision of the spreading record R (double for FP64 storage, float
+// otherwise: the shares then carry ~1e-7 relative rounding, far below the
+// FP32 path's own error).  Vertex positions are read from global memory (one
+// capsule's positions stay in L2).  Float shares need 69 KB of LDS, so two
+// 512-thread workgroups share a CU; double shares take one 1024-thread
+// workgroup per CU.  Each thread gathers up to two nodes.
 template <typename R>
-__global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ sims, Items it,
-                                                     int mode) {
-  __shared__ double px[3][kLdsNodes];
-  __shared__ double pe[9][kLdsEdges];
+constexpr int forces_threads() { return sizeof(R) == 4 ? 512 : 1024; }
+static_assert(2 * 512 >= kLdsNodes, "two nodes per thread cover a template of the LDS force kernel");
+
+// Sum of a node's incident shares, in the template's incidence order.  The
+// share of a role is a fixed combination of the edge's three stored vectors
+// (G0, G3, F1): role 0 -> G0, role 3 -> G3, role 1 -> F1, role 2 (v2) ->
+// -(G0 + G3 + F1); it is evaluated branch-free so lanes of different roles
+// do not diverge.
+template <typename R>
+__device__ __forceinline__ void gather_node(const SimDev& S, const R (*pe)[kLdsEdges], int r0, int r1,
+                                            int e0, double F[3]) {
+  F[0] = F[1] = F[2] = 0.0;
+  for (int rb = r0; rb < r1; rb += 8) {
+    int ents[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ents[k] = rb + k < r1 ? S.inc[rb + k] : -1;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      if (ents[k] < 0) continue;
+      const int e = (ents[k] >> 2) - e0, role = ents[k] & 3;
+      const double c0 = role == 0 ? 1.0 : (role == 2 ? -1.0 : 0.0);
+      const double c3 = role == 3 ? 1.0 : (role == 2 ? -1.0 : 0.0);
+      const double c1 = role == 1 ? 1.0 : (role == 2 ? -1.0 : 0.0);
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        F[a] += c0 * (double)pe[a][e] + c3 * (double)pe[3 + a][e] + c1 * (double)pe[6 + a][e];
+    }
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev* __restrict__ sims,
+                                                                    Items it, int mode) {
+  __shared__ R pe[9][kLdsEdges];
   __shared__ BinTable bt;
   const int tid = threadIdx.x;
+  constexpr int NT = forces_threads<R>();
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
     const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
@@ -202,50 +291,33 @@ __global__ __launch_bounds__(1024) void k_forces_lds(const SimDev* __restrict__ 
     const int nn = S.t_nn[tm], ne = S.t_ne[tm];
     const int row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
-    for (int i = tid; i < nn; i += blockDim.x)
-      for (int a = 0; a < 3; ++a) px[a][i] = S.X[a * ms + off + i];
-    __syncthreads();
-    for (int e = tid; e < ne; e += blockDim.x) {
+    const GLB double* X0 = S.X + off;
+    for (int e = tid; e < ne; e += NT) {
       const GLB int* v = S.ev + 4 * (e0 + e);
       D3 p[4];
-      for (int k = 0; k < 4; ++k) p[k] = {px[0][v[k]], px[1][v[k]], px[2][v[k]]};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int vk = v[k];
+        p[k] = {X0[vk], X0[ms + vk], X0[2 * ms + vk]};
+      }
       D3 G0, G3, F1;
       edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
-      pe[0][e] = G0.x; pe[1][e] = G0.y; pe[2][e] = G0.z;
-      pe[3][e] = G3.x; pe[4][e] = G3.y; pe[5][e] = G3.z;
-      pe[6][e] = F1.x; pe[7][e] = F1.y; pe[8][e] = F1.z;
+      pe[0][e] = (R)G0.x; pe[1][e] = (R)G0.y; pe[2][e] = (R)G0.z;
+      pe[3][e] = (R)G3.x; pe[4][e] = (R)G3.y; pe[5][e] = (R)G3.z;
+      pe[6][e] = (R)F1.x; pe[7][e] = (R)F1.y; pe[8][e] = (R)F1.z;
     }
     __syncthreads();
-    for (int i0 = 0; i0 < nn; i0 += blockDim.x) {
-      const int i = i0 + tid;
-      const bool act = i < nn;
-      double F[3] = {0.0, 0.0, 0.0};
-      const int r0 = act ? S.inc_ptr[row0 + i] : 0, r1 = act ? S.inc_ptr[row0 + i + 1] : 0;
-      // the node's incidence entries, fetched together (a node of a closed
-      // triangulation has 4 x valence entries; 16 covers valence <= 4 in one
-      // batch and larger valences in further batches)
-      for (int rb = r0; rb < r1; rb += 16) {
-      int ents[16];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) ents[k] = rb + k < r1 ? S.inc[rb + k] : -1;
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        if (ents[k] < 0) continue;
-        const int ent = ents[k];
-        const int e = (ent >> 2) - e0, role = ent & 3;
-        for (int a = 0; a < 3; ++a) {
-          double v;
-          if (role == 0) v = pe[a][e];
-          else if (role == 3) v = pe[3 + a][e];
-          else if (role == 1) v = pe[6 + a][e];
-          else v = -(pe[a][e] + pe[3 + a][e] + pe[6 + a][e]);
-          F[a] += v;
-        }
-      }
-      }
-      const double Xp[3] = {act ? px[0][i] : 0.0, act ? px[1][i] : 0.0, act ? px[2][i] : 0.0};
-      emit_nodes<R>(S, bt, act, off + i, Xp, F);
-    }
+    // nodes tid and tid + NT (nn <= kLdsNodes <= 2 NT)
+    const int ia = tid, ib = tid + NT;
+    const bool acta = ia < nn, actb = ib < nn;
+    double Fa[3], Fb[3];
+    gather_node<R>(S, pe, acta ? S.inc_ptr[row0 + ia] : 0, acta ? S.inc_ptr[row0 + ia + 1] : 0, e0, Fa);
+    gather_node<R>(S, pe, actb ? S.inc_ptr[row0 + ib] : 0, actb ? S.inc_ptr[row0 + ib + 1] : 0, e0, Fb);
+    const double Xa[3] = {acta ? X0[ia] : 0.0, acta ? X0[ms + ia] : 0.0, acta ? X0[2 * ms + ia] : 0.0};
+    const double Xb[3] = {actb ? X0[ib] : 0.0, actb ? X0[ms + ib] : 0.0, actb ? X0[2 * ms + ib] : 0.0};
+    emit_nodes<R>(S, bt, acta, off + ia, Xa, Fa);
+    if (nn > NT) emit_nodes<R>(S, bt, actb, off + ib, Xb, Fb);  // uniform
+    __syncthreads();  // shares of this capsule read before the next one's are written
   }
 }
 
@@ -586,87 +658,89 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
                                                            int mode) {
   __shared__ R4<R> ut[kTileCells];
   __shared__ int home[kCandCap];
-  __shared__ int nhome;
+  __shared__ int nhome[2];  // alternate bricks use alternate counters (one barrier fewer)
   const int tid = threadIdx.x;
+  if (tid < 2) nhome[tid] = 0;
+  __syncthreads();
+  int par = 0;
   for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
     const int s = find_sim(it.brick_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int64_t b = item - it.brick_off[s];
+    int cnt = S.bcount[b];
+    if (cnt == 0) continue;  // no node near this brick (uniform)
+    cnt = cnt > kCandCap ? kCandCap : cnt;
     const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
     const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
     const int nb0 = S.nb[0], nb1 = S.nb[1];
-    const int64_t b = item - it.brick_off[s];
     const int bx = (int)(b % nb0), byz = (int)(b / nb0);
     const int ox = bx * kBrick, oy = (byz % nb1) * kBrick, oz = (byz / nb1) * kBrick;
-    int cnt = S.bcount[b];
-    cnt = cnt > kCandCap ? kCandCap : cnt;
-    if (tid == 0) nhome = 0;
-    __syncthreads();
     const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
     const GLB int32_t* list = S.blist + b * kCandCap;
+    // velocity tile: independent of the list, so its loads overlap the
+    // list filtering below
+    const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
+    for (int t = tid; t < kTileCells; t += blockDim.x) {
+      const int tx = t % kTileEdge, ty = (t / kTileEdge) % kTileEdge, tz = t / (kTileEdge * kTileEdge);
+      // periodic axes wrap: the margin spans -1 .. n + 8, which three
+      // turns bring into range for any axis of >= 4 cells
+      const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
+      const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
+      const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
+      const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
+      R vx = (R)0, vy = (R)0, vz = (R)0;
+      if (in) {
+        const R4<R> v = *(const R4<R>*)(u4 + (cx + (int64_t)n0 * (cy + (int64_t)n1 * cz)));
+        vx = v.x;
+        vy = v.y;
+        vz = v.z;
+      }
+      ut[t].x = vx;
+      ut[t].y = vy;
+      ut[t].z = vz;
+    }
     for (int i = tid; i < cnt; i += blockDim.x) {
       const int node = list[i];
       const GLB int32_t* bs = (const GLB int32_t*)(rec + node);
       const int rx = bs[0] - ox, ry = bs[1] - oy, rz = bs[2] - oz;
       if ((unsigned)rx < (unsigned)kBrick && (unsigned)ry < (unsigned)kBrick &&
           (unsigned)rz < (unsigned)kBrick)
-        home[atomicAdd(&nhome, 1)] = node;
+        home[atomicAdd(&nhome[par], 1)] = node;
     }
     __syncthreads();
-    const int nh = nhome;
-    if (nh > 0) {
-      const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
-      for (int t = tid; t < kTileCells; t += blockDim.x) {
-        const int tx = t % kTileEdge, ty = (t / kTileEdge) % kTileEdge, tz = t / (kTileEdge * kTileEdge);
-        // periodic axes wrap: the margin spans -1 .. n + 8, which three
-        // turns bring into range for any axis of >= 4 cells
-        const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
-        const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
-        const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
-        const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
-        R vx = (R)0, vy = (R)0, vz = (R)0;
-        if (in) {
-          const R4<R> v = *(const R4<R>*)(u4 + (cx + (int64_t)n0 * (cy + (int64_t)n1 * cz)));
-          vx = v.x;
-          vy = v.y;
-          vz = v.z;
-        }
-        ut[t].x = vx;
-        ut[t].y = vy;
-        ut[t].z = vz;
-      }
-      __syncthreads();
-      const int64_t ms = (int64_t)S.maxn;
-      for (int j = tid; j < nh; j += blockDim.x) {
-        const int node = home[j];
-        const NodeRec<R> q = *(const NodeRec<R>*)(rec + node);
-        // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
-        const int t0 = (q.base[0] - ox) + kTileEdge * ((q.base[1] - oy) + kTileEdge * (q.base[2] - oz));
-        R sx = (R)0, sy = (R)0, sz = (R)0;
+    const int nh = nhome[par];
+    if (tid == 0) nhome[par ^ 1] = 0;  // the next brick's counter (its last reader passed a barrier)
+    const int64_t ms = (int64_t)S.maxn;
+    for (int j = tid; j < nh; j += blockDim.x) {
+      const int node = home[j];
+      const NodeRec<R> q = *(const NodeRec<R>*)(rec + node);
+      // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
+      const int t0 = (q.base[0] - ox) + kTileEdge * ((q.base[1] - oy) + kTileEdge * (q.base[2] - oz));
+      R sx = (R)0, sy = (R)0, sz = (R)0;
 #pragma unroll
-        for (int dz = 0; dz < 4; ++dz)
+      for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
-          for (int dy = 0; dy < 4; ++dy) {
-            const R wyz = q.w[1][dy] * q.w[2][dz];
-            const int trow = t0 + kTileEdge * (dy + kTileEdge * dz);
+        for (int dy = 0; dy < 4; ++dy) {
+          const R wyz = q.w[1][dy] * q.w[2][dz];
+          const int trow = t0 + kTileEdge * (dy + kTileEdge * dz);
 #pragma unroll
-            for (int dx = 0; dx < 4; ++dx) {
-              const R w = q.w[0][dx] * wyz;
-              const R4<R> v = ut[trow + dx];
-              sx += w * v.x;
-              sy += w * v.y;
-              sz += w * v.z;
-            }
+          for (int dx = 0; dx < 4; ++dx) {
+            const R w = q.w[0][dx] * wyz;
+            const R4<R> v = ut[trow + dx];
+            sx += w * v.x;
+            sy += w * v.y;
+            sz += w * v.z;
           }
-        const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
-        S.U[node] = ux;
-        S.U[ms + node] = uy;
-        S.U[2 * ms + node] = uz;
-        if (mode == 0) {
-          S.X[node] += ux;
-          S.X[ms + node] += uy;
-          S.X[2 * ms + node] += uz;
         }
+      const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
+      S.U[node] = ux;
+      S.U[ms + node] = uy;
+      S.U[2 * ms + node] = uz;
+      if (mode == 0) {
+        S.X[node] += ux;
+        S.X[ms + node] += uy;
+        S.X[2 * ms + node] += uz;
       }
     }
     __syncthreads();
@@ -674,6 +748,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       S.bcount[b] = 0;
       S.bmax[b] = 0u;
     }
+    par ^= 1;
   }
 }
 
@@ -692,7 +767,8 @@ void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
     hipLaunchKernelGGL(k_node_forces<R>, dim3(grid_for(it.mesh_total * kNodeChunks, 1 << 20)), dim3(256), 0,
                        s, sims, it, mode);
   } else {
-    hipLaunchKernelGGL(k_forces_lds<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(1024), 0, s, sims, it, mode);
+    hipLaunchKernelGGL(k_forces_lds<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(forces_threads<R>()), 0, s,
+                       sims, it, mode);
   }
 }
 

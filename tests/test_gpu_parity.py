@@ -148,6 +148,28 @@ def test_ragged_periodic_multi_capsule(storage):
     _compare(spec, g, o, storage)
 
 
+def _short_periodic_spec():
+    """Periodic x and y of 17 cells: the last brick of each is one cell wide,
+    so a stencil across the boundary meets three bricks along the axis."""
+    rng = np.random.default_rng(78)
+    S, T = W.icosphere(2)
+    x1 = S * 3.0 + np.array([16.4, 0.3, 6.6])
+    x2 = W.ellipsoid(S, 4.0, 2.5, 2.5) @ W.random_rotation(rng).T + np.array([8.2, 9.1, 6.9])
+    caps = [W.Capsule(x1 + rng.normal(0, 0.04, x1.shape), x1, T, 0.02, 0.004, ""),
+            W.Capsule(x2, x2.copy(), T, 0.01, 0.002, "")]
+    spec = W.SimSpec(n=(17, 17, 14), tau=0.8, g_body=(1e-5, 5e-6, 0.0), wall=(0, 0, 1), capsules=caps,
+                     delta="peskin4", steps=25)
+    spec.u_hi[2, 0] = 0.005
+    return spec
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_short_periodic_axes(storage):
+    spec = _short_periodic_spec()
+    g, o = _run_pair(spec, storage, 25)
+    _compare(spec, g, o, storage)
+
+
 def test_bitwise_repeatable():
     spec = _ragged_spec()
     a = ibl.Sim.from_spec(spec, storage="f32")
