@@ -31,6 +31,7 @@ import argparse
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -194,7 +195,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the served run")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
-    ap.add_argument("--cache", default=os.path.join(ROOT, "gpurun_out", "rbc_channel_spec.npz"))
+    ap.add_argument("--cache", default=os.path.join(tempfile.gettempdir(), "ibl_rbc_channel_spec.npz"),
+                    help="cache of the generated RBC node arrays ('' disables)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(calibrates the HBM byte counters of a profiler run)")

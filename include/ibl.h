@@ -177,11 +177,12 @@ ibl_status ibl_step_count(ibl_sim sim, int64_t* out_steps);
 /* Phase timing, the GPU counterpart of the paper's coupling-cost table
  * (Table 1): run n_steps timesteps (1 .. 100000) on the simulation's stream,
  * launched one phase at a time with a HIP event after each, and return the
- * mean milliseconds per step of every phase in ms_out[0..4] -- 0 membrane
- * forces and spreading records, 1 force spreading (Eq. (15)), 2 collision and
- * streaming, 3 velocity interpolation (Eq. (14)) and node update, 4 step
- * counter -- and the total elapsed milliseconds of the run in ms_out[5].
- * The state advances by n_steps.  Synchronous. */
+ * mean milliseconds per step of every phase in ms_out[0..3] -- 0 membrane
+ * forces, spreading records and candidate lists, 1 force spreading
+ * (Eq. (15)) fused with collision and streaming, 2 velocity interpolation
+ * (Eq. (14)) and node update, 3 step counter -- and the total elapsed
+ * milliseconds of the run in ms_out[4].  ms_out holds 5 doubles.  The state
+ * advances by n_steps.  Synchronous. */
 ibl_status ibl_profile_phases(ibl_sim sim, int64_t n_steps, double* ms_out);
 
 /* Batching: many independent simulations advanced by one launch per kernel

@@ -15,19 +15,6 @@
 namespace ibl {
 namespace {
 
-// ------------------------------------------------------------------------
-// D3Q19 in this file's order: the rest velocity, the z = 0 plane, then the
-// z = +-1 links.  Opposite directions are neighbours: (1,2), (3,4), ... (17,18).
-// Weights: 1/3 rest, 1/18 axis links, 1/36 diagonal links.
-// ------------------------------------------------------------------------
-constexpr int kCx[kQ] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0};
-constexpr int kCy[kQ] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1};
-constexpr int kCz[kQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1};
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-__host__ __device__ constexpr double wq(int i) {
-  return i == 0 ? 1.0 / 3.0 : ((i <= 4 || i == 9 || i == 10) ? 1.0 / 18.0 : 1.0 / 36.0);
-}
-
 // ---------------------------------------------------------------- storage --
 // Every storage mode keeps the offset h_i = f_i - w_i (the equilibrium at rest
 // subtracted): at low Mach number f_i differs from w_i only in its low bits,
@@ -87,6 +74,28 @@ constexpr int kXcds = 8;
 __device__ __forceinline__ int xcd_block() {
   const int per = (int)gridDim.x / kXcds;
   return (int)(blockIdx.x % kXcds) * per + (int)(blockIdx.x / kXcds);
+}
+
+// Origin (first cell) of brick b.
+__device__ __forceinline__ void brick_origin(const SimDev& S, int64_t b, int& ox, int& oy, int& oz) {
+  const int64_t r = b / S.nb[0];
+  ox = (int)(b - r * S.nb[0]) << S.bsh[0];
+  oy = (int)(r % S.nb[1]) << S.bsh[1];
+  oz = (int)(r / S.nb[1]) << S.bsh[2];
+}
+
+// The four stencil cells from `base` along one axis, relative to the brick
+// origin o (periodic images folded in), and the mask of those inside the
+// brick (0 <= l < size).
+__device__ __forceinline__ void axis_cells(int base, int o, int n, int wall, int size, int l[4], int& mask) {
+  mask = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int c = base - 1 + k;
+    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    l[k] = c - o;
+    mask |= ((unsigned)l[k] < (unsigned)size) ? (1 << k) : 0;
+  }
 }
 
 __device__ __forceinline__ int wrap(int v, int n) {

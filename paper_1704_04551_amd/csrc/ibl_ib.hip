@@ -4,41 +4,28 @@
 //                 takes) every edge of every capsule in parallel (FP64 shares
 //                 to scratch), then every node gathers its incident shares in a
 //                 fixed order and writes its record.
-//   k_forces_lds  one workgroup per capsule.  Node positions are staged in
-//                 LDS; every edge's spring + bending forces on its four
-//                 vertices are computed once (FP64) into LDS; each node then
-//                 gathers its incident edge shares in a fixed order.  Writes
-//                 F, the node's spreading record (stencil base, delta weights,
-//                 F) and appends the node to the candidate lists of the 8^3
-//                 bricks its 4x4x4 stencil touches.
-//   k_spread_fx   FP32 / FP16 storage: one workgroup per brick, one lane per
-//                 candidate node, Eq. (15) in 32-bit fixed point in LDS
-//                 (order-independent integer sums; see the kernel's comment).
-//   k_spread      FP64 storage: one workgroup (8 waves) per brick.  Eq. (15) as
-//                 an ordered, atomic-free scatter into the brick's LDS force
-//                 field.  The
-//                 brick's candidates are grouped by which 4-cell block of
-//                 base cells they fall in along each axis (3 x 3 x 3 groups),
-//                 and sorted by (group, node id).  Two groups whose blocks are
-//                 two apart along some axis have disjoint stencils, so the 27
-//                 groups run in 8 phases of mutually disjoint groups, one wave
-//                 per group, each wave applying its nodes in ascending id
-//                 order (lane = stencil point, plain read-add-write).  Every
-//                 cell therefore receives its shares in a fixed order: the
-//                 result is bitwise reproducible and independent of launch
-//                 geometry and batching.
+//   k_forces_lds  one workgroup per capsule.  Every edge's spring + bending
+//                 forces on its four vertices are computed once (FP64) into
+//                 LDS; each node then gathers its incident edge shares in a
+//                 fixed order.  Writes F, the node's spreading record (stencil
+//                 base, delta weights, F) and appends the node to the
+//                 candidate lists of the lattice bricks its 4x4x4 stencil
+//                 touches.
 //   k_interp      Eq. (14): one workgroup per brick, the brick's velocity and
 //                 its stencil margin in LDS, one lane per home node, fixed
 //                 summation order; X^{n+1} = X^n + U (FP64).  Clears the
 //                 brick's candidate list.
+// Force spreading (Eq. (15)) runs per brick inside the collide-stream kernel
+// (ibl_kernels.hip), from the candidate lists written here.
 #include "ibl_device.h"
 
 namespace ibl {
 namespace {
 
 // The bricks a node's stencil touches.  Along an axis the four stencil cells
-// are consecutive (modulo n), so they meet one or two bricks, a third only
-// on a periodic axis whose last brick is one or two cells wide.  Combination
+// are consecutive (modulo n) and bricks are at least four cells long, so they
+// meet one or two bricks, a third only on a periodic axis whose last brick is
+// one to three cells long.  Combination
 // k = ix + 2 iy + 4 iz takes the first (0) or second (1) brick of each axis.
 struct NodeBricks {
   int br[8];
@@ -48,12 +35,12 @@ struct NodeBricks {
 };
 
 // brick index along one axis of the four stencil cells from `base`
-__device__ __forceinline__ void axis_bricks(int base, int n, int wall, int b[4]) {
+__device__ __forceinline__ void axis_bricks(int base, int n, int wall, int shift, int b[4]) {
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     int c = base - 1 + k;
     if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
-    b[k] = c / kBrick;
+    b[k] = c >> shift;
   }
 }
 
@@ -107,7 +94,7 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int b[4];
-    axis_bricks(q.base[a], S.n[a], S.wall[a], b);
+    axis_bricks(q.base[a], S.n[a], S.wall[a], S.bsh[a], b);
     p0[a] = b[0];
     p1[a] = b[1] != b[0] ? b[1] : (b[2] != b[0] ? b[2] : b[3]);
     h1[a] = p1[a] != b[0];
@@ -214,9 +201,9 @@ __device__ void emit_nodes(const SimDev& S, BinTable& T, bool active, int gid, c
   if (nb.rare) {
     // every distinct brick: the stencil points first of their brick per axis
     int bx[4], by[4], bz[4];
-    axis_bricks(nb.base[0], S.n[0], S.wall[0], bx);
-    axis_bricks(nb.base[1], S.n[1], S.wall[1], by);
-    axis_bricks(nb.base[2], S.n[2], S.wall[2], bz);
+    axis_bricks(nb.base[0], S.n[0], S.wall[0], S.bsh[0], bx);
+    axis_bricks(nb.base[1], S.n[1], S.wall[1], S.bsh[1], by);
+    axis_bricks(nb.base[2], S.n[2], S.wall[2], S.bsh[2], bz);
     for (int kz = 0; kz < 4; ++kz) {
       bool fz = true;
       for (int j = 0; j < kz; ++j) fz &= bz[j] != bz[kz];
@@ -408,261 +395,66 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
   }
 }
 
-// --------------------------------------------------------------- spread --
-constexpr int kSpreadWaves = 8;
-
-template <typename R>
-__global__ __launch_bounds__(64 * kSpreadWaves) void k_spread(const SimDev* __restrict__ sims, Items it,
-                                                              int mode) {
-  __shared__ uint32_t key[kCandCap];
-  __shared__ R gl[3][kBrickCells];
-  __shared__ int gbeg[27], gend[27];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wv = tid >> 6;
-  const int dx = lane & 3, dy = (lane >> 2) & 3, dz = lane >> 4;
-  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
-    const int s = find_sim(it.brick_off, it.nsim, item);
-    const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
-    const int64_t b = item - it.brick_off[s];
-    const int o[3] = {(int)(b % S.nb[0]) * kBrick, (int)((b / S.nb[0]) % S.nb[1]) * kBrick,
-                      (int)(b / ((int64_t)S.nb[0] * S.nb[1])) * kBrick};
-    // an axis can be split into groups only where the stencil offset from the
-    // brick origin is unambiguous: walls, or periodic axes of >= 16 cells
-    bool split[3];
-    for (int a = 0; a < 3; ++a) split[a] = S.wall[a] || S.n[a] >= 16;
-    int cnt = S.bcount[b];
-    if (tid < 27) gbeg[tid] = gend[tid] = 0;
-    __syncthreads();
-    if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
-    cnt = cnt > kCandCap ? kCandCap : cnt;
-    int P = 1;
-    while (P < cnt) P <<= 1;
-    const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
-    for (int i = tid; i < P; i += blockDim.x) {
-      uint32_t k = 0xffffffffu;
-      if (i < cnt) {
-        const int node = S.blist[b * kCandCap + i];
-        int g = 0;
-        for (int a = 2; a >= 0; --a) {
-          int r = rec[node].base[a] - o[a];  // base relative to the brick
-          if (!S.wall[a]) r = r > 8 ? r - S.n[a] : (r < -2 ? r + S.n[a] : r);  // image meeting the brick
-          const int ga = split[a] ? (r + 2) >> 2 : 0;
-          g = 3 * g + ga;
-        }
-        k = ((uint32_t)g << 26) | (uint32_t)node;
-      }
-      key[i] = k;
-    }
-    for (int i = tid; i < kBrickCells; i += blockDim.x) gl[0][i] = gl[1][i] = gl[2][i] = (R)0;
-    __syncthreads();
-    // bitonic sort of key[0..P) ascending: by group, then node id
-    for (int k = 2; k <= P; k <<= 1)
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = tid; i < P; i += blockDim.x) {
-          const int l = i ^ j;
-          if (l > i) {
-            const uint32_t ai = key[i], al = key[l];
-            if ((ai > al) == ((i & k) == 0)) {
-              key[i] = al;
-              key[l] = ai;
-            }
-          }
-        }
-        __syncthreads();
-      }
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const int g = (int)(key[i] >> 26);
-      if (i == 0 || (int)(key[i - 1] >> 26) != g) gbeg[g] = i;
-      if (i == cnt - 1 || (int)(key[i + 1] >> 26) != g) gend[g] = i + 1;
-    }
-    __syncthreads();
-    // 8 phases; in phase (px, py, pz) the groups with (gx, gy, gz) of those
-    // parities run concurrently, one wave each
-    for (int ph = 0; ph < 8; ++ph) {
-      const int p[3] = {ph & 1, (ph >> 1) & 1, ph >> 2};
-      // this wave's group: index wv among the groups of the phase
-      int rem = wv, ga[3];
-      bool have = true;
-      for (int a = 0; a < 3; ++a) {
-        const int choices = p[a] ? 1 : 2;  // parity 0 -> {0, 2}, parity 1 -> {1}
-        ga[a] = p[a] ? 1 : 2 * (rem % choices);
-        rem /= choices;
-      }
-      if (rem > 0) have = false;
-      if (have) {
-        const int g = ga[0] + 3 * (ga[1] + 3 * ga[2]);
-        for (int k = gbeg[g]; k < gend[g]; ++k) {
-          const int node = __builtin_amdgcn_readfirstlane((int)(key[k] & 0x3ffffffu));
-          const NodeRec<R>& q = *(const NodeRec<R>*)(rec + node);
-          int cx = q.base[0] - 1 + dx, cy = q.base[1] - 1 + dy, cz = q.base[2] - 1 + dz;
-          if (!S.wall[0]) cx = cx < 0 ? cx + S.n[0] : (cx >= S.n[0] ? cx - S.n[0] : cx);
-          if (!S.wall[1]) cy = cy < 0 ? cy + S.n[1] : (cy >= S.n[1] ? cy - S.n[1] : cy);
-          if (!S.wall[2]) cz = cz < 0 ? cz + S.n[2] : (cz >= S.n[2] ? cz - S.n[2] : cz);
-          const int lx = cx - o[0], ly = cy - o[1], lz = cz - o[2];
-          if ((unsigned)lx < (unsigned)kBrick && (unsigned)ly < (unsigned)kBrick &&
-              (unsigned)lz < (unsigned)kBrick) {
-            const R w = q.w[0][dx] * q.w[1][dy] * q.w[2][dz];
-            const int li = lx + kBrick * (ly + kBrick * lz);
-            gl[0][li] += w * q.F[0];
-            gl[1][li] += w * q.F[1];
-            gl[2][li] += w * q.F[2];
-          }
-        }
-      }
-      __syncthreads();
-    }
-    // shares that landed on solid layers are dropped here
-    GLB R* g = (GLB R*)S.g;
-    for (int i = tid; i < kBrickCells; i += blockDim.x) {
-      const int x = o[0] + (i % kBrick), y = o[1] + (i / kBrick) % kBrick, z = o[2] + i / (kBrick * kBrick);
-      if (x < S.n[0] && y < S.n[1] && z < S.n[2]) {
-        const bool sol = solid_cell(S, x, y, z);
-        const int64_t c = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
-        g[c] = sol ? (R)0 : gl[0][i];
-        g[S.ncell + c] = sol ? (R)0 : gl[1][i];
-        g[2 * S.ncell + c] = sol ? (R)0 : gl[2][i];
-      }
-    }
-    __syncthreads();
-  }
-}
-
-// ------------------------------------------------------ spread (fixed point) --
-// FP32 / FP16 storage: Eq. (15) accumulated in 32-bit fixed point in LDS.
-// Every share w F is scaled by 2^s, s = 27 - ceil(log2 max|F|) (the largest
-// force component among the brick's candidate nodes), rounded to the nearest
-// integer and added with an integer add.  Integer addition is associative, so
-// the per-cell sums are exact and identical whatever order the lanes and waves
-// run in: the kernel needs no sorting and no ordering between waves, and its
-// result is bitwise reproducible.  Resolution: max|F| * 2^-27 (below
-// binary32's own rounding of a share); headroom: per-cell |sum| up to
-// 16 max|F|, while the delta kernel's partition of unity bounds it by max|F|
-// times the local number of nodes per cell.
-//
-// One lane per candidate node: the node's four stencil cells per axis are
-// mapped into the brick once (periodic images included), giving a per-axis
-// in-brick mask; the lane then walks its 4 x 4 x 4 stencil, skipping points
-// outside the brick.
-constexpr int kSpreadFxThreads = 256;
-
-__device__ __forceinline__ void axis_cells(int base, int o, int n, int wall, int l[4], int& mask) {
-  mask = 0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int c = base - 1 + k;
-    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
-    l[k] = c - o;
-    mask |= ((unsigned)l[k] < (unsigned)kBrick) ? (1 << k) : 0;
-  }
-}
-
-__global__ __launch_bounds__(kSpreadFxThreads) void k_spread_fx(const SimDev* __restrict__ sims,
-                                                                  Items it, int mode) {
-  __shared__ int gq[3][kBrickCells];
-  const int tid = threadIdx.x;
-  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
-    const int s = find_sim(it.brick_off, it.nsim, item);
-    const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
-    const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
-    const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
-    const int nb0 = S.nb[0], nb1 = S.nb[1];
-    const int64_t b = item - it.brick_off[s];
-    const int bx = (int)(b % nb0), byz = (int)(b / nb0);
-    const int ox = bx * kBrick, oy = (byz % nb1) * kBrick, oz = (byz / nb1) * kBrick;
-    int cnt = S.bcount[b];
-    // fixed-point scale of this brick: the largest force component among its
-    // candidates, collected (as an order-independent integer max of float
-    // bits) when the nodes were appended
-    const uint32_t fmx = S.bmax[b];
-    for (int i = tid; i < kBrickCells; i += blockDim.x) gq[0][i] = gq[1][i] = gq[2][i] = 0;
-    if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
-    cnt = cnt > kCandCap ? kCandCap : cnt;
-    __syncthreads();
-    const GLB NodeRec<float>* rec = (const GLB NodeRec<float>*)S.rec;
-    int e2;
-    frexpf(__uint_as_float(fmx), &e2);
-    const int sh = 27 - e2;
-    const float sc = ldexpf(1.0f, sh);
-    const GLB int32_t* list = S.blist + b * kCandCap;
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const NodeRec<float> q = *(const NodeRec<float>*)(rec + list[i]);
-      int lx[4], ly[4], lz[4], mx, my, mz;
-      axis_cells(q.base[0], ox, n0, w0, lx, mx);
-      axis_cells(q.base[1], oy, n1, w1, ly, my);
-      axis_cells(q.base[2], oz, n2, w2, lz, mz);
-      const float fx = q.F[0] * sc, fy = q.F[1] * sc, fz = q.F[2] * sc;
-#pragma unroll
-      for (int dz = 0; dz < 4; ++dz) {
-        if (!((mz >> dz) & 1)) continue;
-#pragma unroll
-        for (int dy = 0; dy < 4; ++dy) {
-          if (!((my >> dy) & 1)) continue;
-          const float wyz = q.w[1][dy] * q.w[2][dz];
-          const float gx = fx * wyz, gy = fy * wyz, gz = fz * wyz;
-          const int row = kBrick * (ly[dy] + kBrick * lz[dz]);
-#pragma unroll
-          for (int dx = 0; dx < 4; ++dx) {
-            if (!((mx >> dx) & 1)) continue;
-            const float wx = q.w[0][dx];
-            const int li = row + lx[dx];
-            atomicAdd(&gq[0][li], __float2int_rn(gx * wx));
-            atomicAdd(&gq[1][li], __float2int_rn(gy * wx));
-            atomicAdd(&gq[2][li], __float2int_rn(gz * wx));
-          }
-        }
-      }
-    }
-    __syncthreads();
-    const float inv = ldexpf(1.0f, -sh);
-    GLB float* g = (GLB float*)S.g;
-    const int64_t nc = S.ncell;
-    for (int i = tid; i < kBrickCells; i += blockDim.x) {
-      const int x = ox + (i & (kBrick - 1)), y = oy + ((i / kBrick) & (kBrick - 1)),
-                z = oz + i / (kBrick * kBrick);
-      if (x < n0 && y < n1 && z < n2) {
-        const bool sol = solid_cell(S, x, y, z);
-        const int64_t c = x + (int64_t)n0 * (y + (int64_t)n1 * z);
-        g[c] = sol ? 0.f : (float)gq[0][i] * inv;
-        g[nc + c] = sol ? 0.f : (float)gq[1][i] * inv;
-        g[2 * nc + c] = sol ? 0.f : (float)gq[2][i] * inv;
-      }
-    }
-    __syncthreads();
-  }
-}
-
 // --------------------------------------------------------------- interp --
 // Eq. (14) per brick.  Every valid node has one home brick, the brick of its
 // base cell, and is on that brick's candidate list.  The workgroup of a brick
-// picks its home nodes off the list, loads the velocity of the brick and of
-// the stencil margin around it (cells o-1 .. o+9 per axis; solid cells hold
-// their wall's velocity) into LDS, and each lane then sums one node's 64
+// loads the velocity of the brick and of the stencil margin around it (cells
+// o-1 .. o+size+1 per axis; solid cells hold their wall's velocity) into LDS;
+// each lane takes one candidate and, if the brick is its home, sums its 64
 // stencil points in a fixed order: the result does not depend on the list's
 // order.  X^{n+1} = X^n + U in FP64.  The workgroup also clears the brick's
 // list for the next step's appends.
-constexpr int kTileEdge = kBrick + 3;
-constexpr int kTileCells = kTileEdge * kTileEdge * kTileEdge;
 constexpr int kInterpThreads = 256;
+// largest margin tile over the brick shapes (64 x 4 x 4 -> 67 x 7 x 7)
+constexpr int kTileMax = (64 + 3) * (kBrickThreads / 64 + 3) * (kBrickZ + 3);
+static_assert((32 + 3) * (kBrickThreads / 32 + 3) * (kBrickZ + 3) <= kTileMax, "tile size");
+static_assert((16 + 3) * (kBrickThreads / 16 + 3) * (kBrickZ + 3) <= kTileMax, "tile size");
 
 __device__ __forceinline__ int margin_wrap(int c, int n) {
+  // the margin spans -1 .. n + 63 + 2; for an axis shorter than the brick the
+  // tile may wrap several times
   c = c < 0 ? c + n : c;
-  c = c >= n ? c - n : c;
-  c = c >= n ? c - n : c;
-  return c >= n ? c - n : c;
+  while (c >= n) c -= n;
+  return c;
+}
+
+template <typename R>
+__device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kTileMax], const NodeRec<R>& q,
+                                            int node, int ox, int oy, int oz, int ex, int exy, int mode) {
+  // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
+  const int t0 = (q.base[0] - ox) + ex * (q.base[1] - oy) + exy * (q.base[2] - oz);
+  R sx = (R)0, sy = (R)0, sz = (R)0;
+#pragma unroll
+  for (int dz = 0; dz < 4; ++dz)
+#pragma unroll
+    for (int dy = 0; dy < 4; ++dy) {
+      const R wyz = q.w[1][dy] * q.w[2][dz];
+      const int trow = t0 + ex * dy + exy * dz;
+#pragma unroll
+      for (int dx = 0; dx < 4; ++dx) {
+        const R w = q.w[0][dx] * wyz;
+        sx += w * ut[0][trow + dx];
+        sy += w * ut[1][trow + dx];
+        sz += w * ut[2][trow + dx];
+      }
+    }
+  const int64_t ms = (int64_t)S.maxn;
+  const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
+  S.U[node] = ux;
+  S.U[ms + node] = uy;
+  S.U[2 * ms + node] = uz;
+  if (mode == 0) {
+    S.X[node] += ux;
+    S.X[ms + node] += uy;
+    S.X[2 * ms + node] += uz;
+  }
 }
 
 template <typename R>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restrict__ sims, Items it,
                                                            int mode) {
-  __shared__ R4<R> ut[kTileCells];
-  __shared__ int home[kCandCap];
-  __shared__ int nhome[2];  // alternate bricks use alternate counters (one barrier fewer)
+  __shared__ R ut[3][kTileMax];
   const int tid = threadIdx.x;
-  if (tid < 2) nhome[tid] = 0;
-  __syncthreads();
-  int par = 0;
   for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
     const int s = find_sim(it.brick_off, it.nsim, item);
     const SimDev& S = sims[s];
@@ -673,18 +465,23 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
     cnt = cnt > kCandCap ? kCandCap : cnt;
     const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
     const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
-    const int nb0 = S.nb[0], nb1 = S.nb[1];
-    const int bx = (int)(b % nb0), byz = (int)(b / nb0);
-    const int ox = bx * kBrick, oy = (byz % nb1) * kBrick, oz = (byz / nb1) * kBrick;
+    int ox, oy, oz;
+    brick_origin(S, b, ox, oy, oz);
+    const int ex = S.bs[0] + 3, ey = S.bs[1] + 3, exy = ex * ey, ncells = exy * (S.bs[2] + 3);
+    const int bx = S.bs[0], by = S.bs[1], bz = S.bs[2];
     const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
     const GLB int32_t* list = S.blist + b * kCandCap;
-    // velocity tile: independent of the list, so its loads overlap the
-    // list filtering below
+    // this lane's first candidate, fetched before the tile so both are in
+    // flight together
+    int node = -1;
+    NodeRec<R> q;
+    if (tid < cnt) {
+      node = list[tid];
+      q = *(const NodeRec<R>*)(rec + node);
+    }
     const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
-    for (int t = tid; t < kTileCells; t += blockDim.x) {
-      const int tx = t % kTileEdge, ty = (t / kTileEdge) % kTileEdge, tz = t / (kTileEdge * kTileEdge);
-      // periodic axes wrap: the margin spans -1 .. n + 8, which three
-      // turns bring into range for any axis of >= 4 cells
+    for (int t = tid; t < ncells; t += blockDim.x) {
+      const int tz = t / exy, r = t - tz * exy, ty = r / ex, tx = r - ty * ex;
       const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
       const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
       const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
@@ -696,59 +493,29 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
         vy = v.y;
         vz = v.z;
       }
-      ut[t].x = vx;
-      ut[t].y = vy;
-      ut[t].z = vz;
-    }
-    for (int i = tid; i < cnt; i += blockDim.x) {
-      const int node = list[i];
-      const GLB int32_t* bs = (const GLB int32_t*)(rec + node);
-      const int rx = bs[0] - ox, ry = bs[1] - oy, rz = bs[2] - oz;
-      if ((unsigned)rx < (unsigned)kBrick && (unsigned)ry < (unsigned)kBrick &&
-          (unsigned)rz < (unsigned)kBrick)
-        home[atomicAdd(&nhome[par], 1)] = node;
+      ut[0][t] = vx;
+      ut[1][t] = vy;
+      ut[2][t] = vz;
     }
     __syncthreads();
-    const int nh = nhome[par];
-    if (tid == 0) nhome[par ^ 1] = 0;  // the next brick's counter (its last reader passed a barrier)
-    const int64_t ms = (int64_t)S.maxn;
-    for (int j = tid; j < nh; j += blockDim.x) {
-      const int node = home[j];
-      const NodeRec<R> q = *(const NodeRec<R>*)(rec + node);
-      // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
-      const int t0 = (q.base[0] - ox) + kTileEdge * ((q.base[1] - oy) + kTileEdge * (q.base[2] - oz));
-      R sx = (R)0, sy = (R)0, sz = (R)0;
-#pragma unroll
-      for (int dz = 0; dz < 4; ++dz)
-#pragma unroll
-        for (int dy = 0; dy < 4; ++dy) {
-          const R wyz = q.w[1][dy] * q.w[2][dz];
-          const int trow = t0 + kTileEdge * (dy + kTileEdge * dz);
-#pragma unroll
-          for (int dx = 0; dx < 4; ++dx) {
-            const R w = q.w[0][dx] * wyz;
-            const R4<R> v = ut[trow + dx];
-            sx += w * v.x;
-            sy += w * v.y;
-            sz += w * v.z;
-          }
+    // one lane per candidate; a node is interpolated by its home brick only
+    for (int i0 = 0; i0 < cnt; i0 += blockDim.x) {
+      if (i0 > 0) {
+        node = -1;
+        if (i0 + tid < cnt) {
+          node = list[i0 + tid];
+          q = *(const NodeRec<R>*)(rec + node);
         }
-      const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
-      S.U[node] = ux;
-      S.U[ms + node] = uy;
-      S.U[2 * ms + node] = uz;
-      if (mode == 0) {
-        S.X[node] += ux;
-        S.X[ms + node] += uy;
-        S.X[2 * ms + node] += uz;
       }
+      if (node >= 0 && (unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
+          (unsigned)(q.base[2] - oz) < (unsigned)bz)
+        interp_node<R>(S, ut, q, node, ox, oy, oz, ex, exy, mode);
     }
     __syncthreads();
     if (tid == 0) {
       S.bcount[b] = 0;
       S.bmax[b] = 0u;
     }
-    par ^= 1;
   }
 }
 
@@ -777,13 +544,6 @@ void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
 void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
   if (storage == kF64) forces_impl<double>(sims, it, mode, s);
   else forces_impl<float>(sims, it, mode, s);
-}
-
-void launch_spread(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
-  if (it.mesh_total <= 0 || it.brick_total <= 0) return;
-  const dim3 grid(grid_for(it.brick_total, 1 << 20));
-  if (storage == kF64) hipLaunchKernelGGL(k_spread<double>, grid, dim3(64 * kSpreadWaves), 0, s, sims, it, mode);
-  else hipLaunchKernelGGL(k_spread_fx, grid, dim3(kSpreadFxThreads), 0, s, sims, it, mode);
 }
 
 void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {

@@ -19,17 +19,31 @@
 namespace ibl {
 
 constexpr int kQ = 19;
-constexpr int kBrick = 8;            // edge of the cubic bricks used for spreading
-constexpr int kBrickCells = kBrick * kBrick * kBrick;
-constexpr int kCandCap = 2048;       // candidate nodes per brick
-constexpr int kLatticeBlock = 256;   // threads per lattice work item
-constexpr int kLatX = 64;            // lattice work item: 64 cells along x ...
-constexpr int kLatY = 4;             // ... by 4 rows along y
-constexpr int kNodesPerItem = 64;    // nodes per interpolation work item (16 lanes each, 4 chains)
+// The lattice is processed in bricks of bs[0] x bs[1] x kBrickZ cells with
+// bs[0] x bs[1] = kBrickThreads: one workgroup per brick, each thread a column
+// of kBrickZ cells.  bs[0] (16, 32 or 64) is chosen per simulation.
+constexpr int kBrickThreads = 256;
+constexpr int kBrickZ = 4;
+constexpr int kBrickCells = kBrickThreads * kBrickZ;
+constexpr int kCandCap = 4096;       // candidate nodes per brick
+constexpr int kLatticeBlock = 256;   // threads of the reduction work items
 constexpr int kLdsNodes = 642;       // template size handled by the LDS force kernel (icosphere level 3)
 constexpr int kLdsEdges = 1920;
 constexpr int kReduceItemCells = 4096;
 constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup per mesh)
+
+// ------------------------------------------------------------------------
+// D3Q19 in the library's order: the rest velocity, the z = 0 plane, then the
+// z = +-1 links.  Opposite directions are neighbours: (1,2), (3,4), ... (17,18).
+// Weights: 1/3 rest, 1/18 axis links, 1/36 diagonal links.
+// ------------------------------------------------------------------------
+constexpr int kCx[kQ] = {0, 1, -1, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0};
+constexpr int kCy[kQ] = {0, 0, 0, 1, -1, 1, -1, -1, 1, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1};
+constexpr int kCz[kQ] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 1, -1};
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr double wq(int i) {
+  return i == 0 ? 1.0 / 3.0 : ((i <= 4 || i == 9 || i == 10) ? 1.0 / 18.0 : 1.0 / 36.0);
+}
 
 enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2 };
 enum Delta : int { kCos = 0, kPeskin4 = 1 };
@@ -61,20 +75,24 @@ struct SimDev {
   int32_t wall[3];
   int64_t ncell;
   int32_t nb[3];          // bricks per axis
+  int32_t bs[3];          // brick size per axis (powers of two)
+  int32_t bsh[3];         // log2 of bs
   int32_t delta;
   int64_t nbrick;
   double tau;
   double gb[3];
   double ulo[3][3];
   double uhi[3][3];
+  double bbw[kQ][6];      // moving-wall term 6 w_q (c_q . u_wall) of a bounce-back link, per
+                          // direction and wall layer (2 * axis + [hi side])
   int32_t has_ib;         // 1 when meshes are present
   int32_t nnodes;
   int32_t nmeshes;
   int32_t maxn;           // SoA stride of the node arrays (capacity)
   // state
   IBL_G(void) f[2];             // populations, [19][ncell] in storage format
-  IBL_G(void) u;                // [3][ncell] velocity (compute precision)
-  IBL_G(void) g;                // [3][ncell] spread force (compute precision)
+  IBL_G(void) u;                // [ncell] velocity as 4-vectors (compute precision)
+  IBL_G(void) g;                // [3][ncell] spread force (compute precision; observation only)
   IBL_G(void) rho;              // [ncell] density (observation only)
   IBL_G(double) X;              // [3][max_nodes] positions
   IBL_G(double) F;              // [3][max_nodes] membrane forces
@@ -111,30 +129,30 @@ struct SimDev {
 // Work-item prefix tables of a launch set (one simulation or a batch).
 struct Items {
   int32_t nsim;
-  int32_t lat_total, red_total, mesh_total, brick_total, node_total;
+  int32_t lat_total;         // bricks (every simulation)
+  int32_t red_total;         // reduction items
+  int32_t mesh_total;        // capsules
+  int32_t brick_total;       // bricks of simulations with capsules (interpolation)
   int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
   int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;
   const int32_t* brick_off;
-  const int32_t* node_off;
 };
 
 // Phases of one timestep, in launch order.
 enum Phase : int {
   kPhaseForces = 0,   // membrane forces, spreading records, candidate lists
-  kPhaseSpread = 1,   // force spreading into the per-cell force field
-  kPhaseLattice = 2,  // moments, collision, streaming (u^n written)
-  kPhaseInterp = 3,   // velocity interpolation and node update
-  kPhaseAdvance = 4,  // step counter
-  kNumPhases = 5
+  kPhaseLattice = 1,  // per brick: force spreading, moments, collision, streaming (u^n written)
+  kPhaseInterp = 2,   // velocity interpolation and node update
+  kPhaseAdvance = 3,  // step counter
+  kNumPhases = 4
 };
 
 // Kernel launchers.  mode: 0 = timestep, 1 = observe.
 // ibl_ib.hip: immersed-boundary phases.
 void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
-void launch_spread(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
 void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
 // ibl_kernels.hip: lattice phases and dispatch.
 hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int init_axis_profile,

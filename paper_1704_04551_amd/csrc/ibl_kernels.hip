@@ -2,12 +2,13 @@
 //
 // Per timestep, on one stream:
 //   k_forces   membrane forces, spreading records, candidate lists (ibl_ib.hip)
-//   k_spread   force spreading into the per-cell force field (ibl_ib.hip)
-//   k_lattice  one thread per cell: moments with the half-force shift
-//              (Eq. (3)), BGK collision with the forcing term (Eq. (1), (2),
-//              (4)), push streaming into the other A/B copy with periodic wrap
-//              and halfway bounce-back (moving-wall term); u^n is written for
-//              the interpolation.
+//   k_lattice  one workgroup per lattice brick: force spreading of the
+//              brick's candidate nodes into LDS (Eq. (15), fixed-point
+//              integer sums), then per cell the moments with the half-force
+//              shift (Eq. (3)), BGK collision with the forcing term (Eq. (1),
+//              (2), (4)) and pull streaming with periodic wrap and halfway
+//              bounce-back (moving-wall term); u^n is written for the
+//              interpolation.  The force field never leaves LDS.
 //   k_interp   velocity interpolation and node update (ibl_ib.hip)
 //   k_advance  per simulation: step counter (A/B parity) and remaining steps.
 // Every kernel walks a flattened (simulation, work item) list, so one launch
@@ -17,91 +18,158 @@
 namespace ibl {
 namespace {
 
-__device__ __forceinline__ bool lat_cell(const SimDev& S, int local_item, int tid, int& x, int& y,
-                                         int& z) {
-  // a work item is kLatticeBlock consecutive cells in memory order; the item's
-  // first cell is split once (uniform), each thread then walks forward
-  const int64_t c0 = (int64_t)local_item * kLatticeBlock;
-  if (c0 + tid >= S.ncell) return false;
-  const int nx = S.n[0], ny = S.n[1];
-  int x0 = (int)(c0 % nx);
-  const int64_t r0 = c0 / nx;
-  y = (int)(r0 % ny);
-  z = (int)(r0 / ny);
-  x = x0 + tid;
-  while (x >= nx) {
-    x -= nx;
-    if (++y == ny) {
-      y = 0;
-      ++z;
-    }
+// -------------------------------------------------------------- streaming --
+// The populations are stored post-collision (f* of the previous step) and
+// streamed on read ("pull"): f_q(x) = f*_q(x - c_q).  Where x - c_q is a wall
+// layer, halfway bounce-back returns the cell's own opposite population with
+// the moving-wall term: f_q(x) = f*_opp(q)(x) + 6 w_q (c_q . u_wall), u_wall
+// the velocity of the first wall axis (x, y, z order) whose layer x - c_q is.
+// Writes are aligned (each cell writes its own populations); only the reads
+// are shifted.
+
+// Source of direction q for fluid cell (x, y, z): the element index of the
+// value to read, and the bounce-back wall layer (2 * axis + [hi side]) or -1.
+// Cell indices fit in 32 bits (the descriptor check bounds the lattice).
+__device__ __forceinline__ int pull_source(const SimDev& S, int q, int x, int y, int z, int cell, int& layer) {
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int xs = x - kCx[q], ys = y - kCy[q], zs = z - kCz[q];
+  const int sy = nx, sz = nx * ny;
+  int sc = cell - kCx[q] - sy * kCy[q] - sz * kCz[q];
+  // periodic wrap: one axis length in index units (nx, nx ny, nx ny nz)
+  if (kCx[q] && !S.wall[0]) sc += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+  if (kCy[q] && !S.wall[1]) sc += ys < 0 ? sz : (ys >= ny ? -sz : 0);
+  if (kCz[q] && !S.wall[2]) sc += zs < 0 ? (int)S.ncell : (zs >= nz ? -(int)S.ncell : 0);
+  const bool bx = kCx[q] && S.wall[0] && (xs == 0 || xs == nx - 1);
+  const bool by = kCy[q] && S.wall[1] && (ys == 0 || ys == ny - 1);
+  const bool bz = kCz[q] && S.wall[2] && (zs == 0 || zs == nz - 1);
+  layer = bx ? (xs != 0) : (by ? 2 + (ys != 0) : (bz ? 4 + (zs != 0) : -1));
+  return layer >= 0 ? cell : sc;
+}
+
+template <int ST>
+__device__ __forceinline__ void pull_cell(const SimDev& S, const GLB typename Store<ST>::T* src, int x, int y,
+                                          int z, int64_t cell, RealOf<ST> h[kQ]) {
+  using R = RealOf<ST>;
+  using T = typename Store<ST>::T;
+  const int64_t nc = S.ncell;
+  // branch-free addresses, so the 19 loads issue together.  Each load is a
+  // uniform base (population min(q, opp q)) plus a 32-bit byte offset: the
+  // descriptor check keeps 2 ncell elements below 2^32 bytes.
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int layer;
+    const int sc = pull_source(S, q, x, y, z, (int)cell, layer);
+    const int plo = q < opp(q) ? q : opp(q);
+    const uint32_t el = (uint32_t)(((layer >= 0 ? opp(q) : q) - plo) * (int)nc + sc);
+    const GLB char* base = (const GLB char*)(src + (int64_t)plo * nc);
+    h[q] = Store<ST>::h((const GLB T*)(base + el * (uint32_t)sizeof(T)), 0, q);
   }
-  return true;
+  // moving-wall term of the bounce-back links
+#pragma unroll
+  for (int q = 1; q < kQ; ++q) {
+    int layer;
+    (void)pull_source(S, q, x, y, z, (int)cell, layer);
+    if (layer >= 0) h[q] += (R)S.bbw[q][layer];
+  }
 }
 
 // ------------------------------------------------------------------ init --
 template <int ST>
-__global__ __launch_bounds__(kLatticeBlock) void k_init(const SimDev* __restrict__ sims, Items it,
-                                                        int profile) {
+__device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
+  const int64_t cell = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
+  const int c[3] = {x, y, z};
+  GLB R4<R>* u = (GLB R4<R>*)S.u;
+  GLB R* g = (GLB R*)S.g;
+  GLB R* rho = (GLB R*)S.rho;
+  for (int a = 0; a < 3; ++a) g[a * S.ncell + cell] = (R)0;
+  rho[cell] = (R)0;
+  GLB T* f0 = (GLB T*)S.f[0];
+  GLB T* f1 = (GLB T*)S.f[1];
+  // solid layer: hold the velocity of the first wall axis it belongs to
+  int sa = -1;
+  for (int a = 0; a < 3; ++a)
+    if (sa < 0 && S.wall[a] && (c[a] == 0 || c[a] == S.n[a] - 1)) sa = a;
+  double u0[3] = {0.0, 0.0, 0.0};
+  if (sa >= 0) {
+    const double* v = (c[sa] == 0) ? S.ulo[sa] : S.uhi[sa];
+    *(R4<R>*)(u + cell) = R4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) {
+      Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)0);
+      Store<ST>::put(f1, (int64_t)q * S.ncell + cell, q, (R)0);
+    }
+    return;
+  }
+  // initial velocity u0 at a fluid cell: rest, or the linear profile across
+  // the (last) wall axis
+  int pa = -1;
+  if (profile)
+    for (int a = 0; a < 3; ++a)
+      if (S.wall[a]) pa = a;
+  auto u_init = [&](const int cc[3], double uo[3]) {
+    uo[0] = uo[1] = uo[2] = 0.0;
+    if (pa >= 0) {
+      const double sfrac = ((double)cc[pa] - 0.5) / (double)(S.n[pa] - 2);
+      for (int a = 0; a < 3; ++a) uo[a] = S.ulo[pa][a] + (S.uhi[pa][a] - S.ulo[pa][a]) * sfrac;
+    }
+  };
+  // f_eq(rho = 1, v) - w_q, Eq. (2)
+  auto h_eq = [](int q, const double v[3]) {
+    const double cu = kCx[q] * v[0] + kCy[q] * v[1] + kCz[q] * v[2];
+    const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+    return wq(q) * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv);
+  };
+  u_init(c, u0);
+  *(R4<R>*)(u + cell) = R4<R>{(R)u0[0], (R)u0[1], (R)u0[2], (R)0};
+  // stored populations are post-collision values that the first step's
+  // pull turns into f_eq(1, u0): the one read by the consumer x + c_q, or,
+  // where x + c_q is a wall layer, the bounce-back source of x itself
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int cn[3] = {x + kCx[q], y + kCy[q], z + kCz[q]};
+    int wall_axis = -1;
+    for (int a = 0; a < 3; ++a) {
+      if (!S.wall[a]) cn[a] = cn[a] < 0 ? cn[a] + S.n[a] : (cn[a] >= S.n[a] ? cn[a] - S.n[a] : cn[a]);
+      else if (wall_axis < 0 && (cn[a] == 0 || cn[a] == S.n[a] - 1)) wall_axis = a;
+    }
+    double hq;
+    if (q != 0 && wall_axis >= 0) {
+      const double* uw = cn[wall_axis] == 0 ? S.ulo[wall_axis] : S.uhi[wall_axis];
+      hq = h_eq(opp(q), u0) + 6.0 * wq(q) * (kCx[q] * uw[0] + kCy[q] * uw[1] + kCz[q] * uw[2]);
+    } else {
+      double uc[3];
+      u_init(cn, uc);
+      hq = h_eq(q, uc);
+    }
+    Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)hq);
+    Store<ST>::put(f1, (int64_t)q * S.ncell + cell, q, (R)hq);
+  }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict__ sims, Items it,
+                                                        int profile) {
+  const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.lat_total; item += gridDim.x) {
     const int s = find_sim(it.lat_off, it.nsim, item);
     const SimDev& S = sims[s];
-    int x, y, z;
-    if (!lat_cell(S, item - it.lat_off[s], threadIdx.x, x, y, z)) continue;
-    const int64_t cell = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
-    if (cell < S.nbrick) {
-      S.bcount[cell] = 0;
-      S.bmax[cell] = 0u;
-    }
-    if (cell == 0) {  // every control word: the arena may hold a previous user's data
-      *S.step = 0;
-      *S.remaining = 0;
-      *S.health = 0u;
-    }
-    const int c[3] = {x, y, z};
-    GLB R4<R>* u = (GLB R4<R>*)S.u;
-    GLB R* g = (GLB R*)S.g;
-    GLB R* rho = (GLB R*)S.rho;
-    for (int a = 0; a < 3; ++a) g[a * S.ncell + cell] = (R)0;
-    rho[cell] = (R)0;
-    GLB T* f0 = (GLB T*)S.f[0];
-    GLB T* f1 = (GLB T*)S.f[1];
-    // solid layer: hold the velocity of the first wall axis it belongs to
-    int sa = -1;
-    for (int a = 0; a < 3; ++a)
-      if (sa < 0 && S.wall[a] && (c[a] == 0 || c[a] == S.n[a] - 1)) sa = a;
-    double u0[3] = {0.0, 0.0, 0.0};
-    if (sa >= 0) {
-      const double* v = (c[sa] == 0) ? S.ulo[sa] : S.uhi[sa];
-      *(R4<R>*)(u + cell) = R4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
-#pragma unroll
-      for (int q = 0; q < kQ; ++q) {
-        Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)0);
-        Store<ST>::put(f1, (int64_t)q * S.ncell + cell, q, (R)0);
-      }
-      continue;
-    }
-    if (profile) {
-      int pa = -1;
-      for (int a = 0; a < 3; ++a)
-        if (S.wall[a]) pa = a;
-      if (pa >= 0) {
-        double sfrac = ((double)c[pa] - 0.5) / (double)(S.n[pa] - 2);
-        for (int a = 0; a < 3; ++a) u0[a] = S.ulo[pa][a] + (S.uhi[pa][a] - S.ulo[pa][a]) * sfrac;
+    const int64_t b = item - it.lat_off[s];
+    if (tid == 0) {  // the arena may hold a previous user's data
+      S.bcount[b] = 0;
+      S.bmax[b] = 0u;
+      if (b == 0) {
+        *S.step = 0;
+        *S.remaining = 0;
+        *S.health = 0u;
       }
     }
-    *(R4<R>*)(u + cell) = R4<R>{(R)u0[0], (R)u0[1], (R)u0[2], (R)0};
-    const double usq = u0[0] * u0[0] + u0[1] * u0[1] + u0[2] * u0[2];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const double cu = kCx[q] * u0[0] + kCy[q] * u0[1] + kCz[q] * u0[2];
-      // f_eq(rho = 1) - w_q, Eq. (2)
-      const double hq = wq(q) * (3.0 * cu + 4.5 * cu * cu - 1.5 * usq);
-      Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)hq);
-      Store<ST>::put(f1, (int64_t)q * S.ncell + cell, q, (R)hq);
-    }
+    int ox, oy, oz;
+    brick_origin(S, b, ox, oy, oz);
+    const int x = ox + (tid & (S.bs[0] - 1)), y = oy + (tid >> S.bsh[0]);
+    if (x >= S.n[0] || y >= S.n[1]) continue;
+    for (int k = 0; k < kBrickZ && oz + k < S.n[2]; ++k) init_cell<ST>(S, x, y, oz + k, profile);
   }
 }
 
@@ -124,97 +192,178 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
 }
 
 // -------------------------------------------------------------- lattice --
+// Fixed-point accumulator of the spread force: every share w F is scaled by
+// 2^s, s = kBits - e where 2^e bounds the largest force component among the
+// brick's candidates (collected as an order-independent integer max of float
+// bits when the nodes were appended), rounded to the nearest integer and
+// added with an integer LDS atomic.  Integer addition is associative, so the
+// per-cell sums are exact and identical whatever order the lanes and waves
+// run in: bitwise reproducible without sorting.  Resolution max|F| 2^-kBits
+// (below the rounding of one share in the compute precision); headroom 2^4
+// (31 - 27, 63 - 58) times max|F| per cell, while the delta kernel's
+// partition of unity bounds a cell's sum by max|F| times the nodes per cell.
+template <typename R>
+struct FixAcc;
+template <>
+struct FixAcc<float> {
+  using A = int32_t;
+  static constexpr int kBits = 27;
+  __device__ static A fix(float v) { return __float2int_rn(v); }
+  __device__ static void add(A* p, A v) { atomicAdd(p, v); }
+};
+template <>
+struct FixAcc<double> {
+  using A = long long;
+  static constexpr int kBits = 58;
+  __device__ static A fix(double v) { return __double2ll_rn(v); }
+  __device__ static void add(A* p, A v) { atomicAdd((unsigned long long*)p, (unsigned long long)v); }
+};
+
 template <int ST>
-__global__ __launch_bounds__(kLatticeBlock) void k_lattice(const SimDev* __restrict__ sims,
+__global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
+  using FA = FixAcc<R>;
+  using A = typename FA::A;
+  __shared__ A gq[3][kBrickCells];
+  const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.lat_total; item += gridDim.x) {
     const int s = find_sim(it.lat_off, it.nsim, item);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;
-    int x, y, z;
-    if (!lat_cell(S, item - it.lat_off[s], threadIdx.x, x, y, z)) continue;
+    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    const int64_t b = item - it.lat_off[s];
+    int ox, oy, oz;
+    brick_origin(S, b, ox, oy, oz);
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-    const int64_t cell = x + (int64_t)nx * (y + (int64_t)ny * z);
-    GLB R4<R>* uf = (GLB R4<R>*)S.u;
-    const int64_t nc = S.ncell;
-    if (solid_cell(S, x, y, z)) {
-      if (mode == 1) {
-        GLB R* rf = (GLB R*)S.rho;
-        rf[cell] = (R)0;
+    const int bx = S.bs[0], by = S.bs[1], bz = S.bs[2];
+    // ---- force spreading, Eq. (15): the brick's candidates, one per lane
+    int cnt = S.has_ib ? S.bcount[b] : 0;
+    const bool ib = cnt > 0;  // uniform
+    R inv = (R)0;
+    if (ib) {
+      const uint32_t fmx = S.bmax[b];
+      if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
+      cnt = cnt > kCandCap ? kCandCap : cnt;
+      const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
+      const GLB int32_t* list = S.blist + b * kCandCap;
+      // this lane's first candidate, fetched before the field is cleared
+      NodeRec<R> q;
+      if (tid < cnt) q = *(const NodeRec<R>*)(rec + list[tid]);
+#pragma unroll
+      for (int k = 0; k < kBrickZ; ++k) gq[0][tid + kBrickThreads * k] = gq[1][tid + kBrickThreads * k] =
+          gq[2][tid + kBrickThreads * k] = (A)0;
+      __syncthreads();
+      int e2;
+      frexpf(__uint_as_float(fmx), &e2);
+      int sh = FA::kBits - e2;
+      sh = sh > 120 ? 120 : sh;  // forces below ~1e-28: their shares round to zero
+      const R sc = (R)ldexp(1.0, sh);
+      inv = (R)ldexp(1.0, -sh);
+      for (int i = tid; i < cnt; i += blockDim.x) {
+        if (i != tid) q = *(const NodeRec<R>*)(rec + list[i]);
+        int lx[4], ly[4], lz[4], mx, my, mz;
+        axis_cells(q.base[0], ox, nx, S.wall[0], bx, lx, mx);
+        axis_cells(q.base[1], oy, ny, S.wall[1], by, ly, my);
+        axis_cells(q.base[2], oz, nz, S.wall[2], bz, lz, mz);
+        const R fx = q.F[0] * sc, fy = q.F[1] * sc, fz = q.F[2] * sc;
+#pragma unroll
+        for (int dz = 0; dz < 4; ++dz) {
+          if (!((mz >> dz) & 1)) continue;
+#pragma unroll
+          for (int dy = 0; dy < 4; ++dy) {
+            if (!((my >> dy) & 1)) continue;
+            const R wyz = q.w[1][dy] * q.w[2][dz];
+            const R gx = fx * wyz, gy = fy * wyz, gz = fz * wyz;
+            const int row = bx * ly[dy] + kBrickThreads * lz[dz];
+#pragma unroll
+            for (int dx = 0; dx < 4; ++dx) {
+              if (!((mx >> dx) & 1)) continue;
+              const R wx = q.w[0][dx];
+              const int li = row + lx[dx];
+              FA::add(&gq[0][li], FA::fix(gx * wx));
+              FA::add(&gq[1][li], FA::fix(gy * wx));
+              FA::add(&gq[2][li], FA::fix(gz * wx));
+            }
+          }
+        }
       }
-      continue;
+      __syncthreads();
     }
-    const int par = (int)(*S.step & 1);
-    const GLB T* src = (const GLB T*)S.f[par];
-    R h[kQ];
+    // ---- collide-stream, a column of kBrickZ cells per thread
+    const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
+    if (x < nx && y < ny) {
+      const int64_t nc = S.ncell;
+      const int par = (int)(*S.step & 1);
+      const GLB T* src = (const GLB T*)S.f[par];
+      GLB T* dst = (GLB T*)S.f[par ^ 1];
+      GLB R4<R>* uf = (GLB R4<R>*)S.u;
+      const R om = (R)(1.0 / S.tau);
+      const R pre = (R)(1.0 - 0.5 / S.tau);
+#pragma unroll 1
+      for (int k = 0; k < kBrickZ; ++k) {
+        const int z = oz + k;
+        if (z >= nz) break;
+        const int64_t cell = x + (int64_t)nx * (y + (int64_t)ny * z);
+        const int li = tid + kBrickThreads * k;
+        if (solid_cell(S, x, y, z)) {
+          if (mode == 1) {
+            ((GLB R*)S.rho)[cell] = (R)0;
+            GLB R* gf = (GLB R*)S.g;
+            gf[cell] = gf[nc + cell] = gf[2 * nc + cell] = (R)0;
+          }
+          continue;
+        }
+        R h[kQ];
+        pull_cell<ST>(S, src, x, y, z, cell, h);
+        // moments, Eq. (3): rho = sum f = 1 + sum h ; rho u = sum h c + g/2
+        R drho = (R)0, jx = (R)0, jy = (R)0, jz = (R)0;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) h[q] = Store<ST>::h(src, (int64_t)q * nc + cell, q);
-    // moments, Eq. (3): rho = sum f = 1 + sum h ; rho u = sum h c + g/2
-    R drho = (R)0, jx = (R)0, jy = (R)0, jz = (R)0;
+        for (int q = 0; q < kQ; ++q) {
+          drho += h[q];
+          if (kCx[q]) jx += kCx[q] > 0 ? h[q] : -h[q];
+          if (kCy[q]) jy += kCy[q] > 0 ? h[q] : -h[q];
+          if (kCz[q]) jz += kCz[q] > 0 ? h[q] : -h[q];
+        }
+        R gix = (R)0, giy = (R)0, giz = (R)0;  // spread force g_IB
+        if (ib) {
+          gix = (R)gq[0][li] * inv;
+          giy = (R)gq[1][li] * inv;
+          giz = (R)gq[2][li] * inv;
+        }
+        const R gx = (R)S.gb[0] + gix, gy = (R)S.gb[1] + giy, gz = (R)S.gb[2] + giz;
+        const R rho = (R)1 + drho;
+        const R irho = (R)1 / rho;
+        const R ux = (jx + (R)0.5 * gx) * irho;
+        const R uy = (jy + (R)0.5 * gy) * irho;
+        const R uz = (jz + (R)0.5 * gz) * irho;
+        if (mode == 1) {
+          ((GLB R*)S.rho)[cell] = rho;
+          *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
+          GLB R* gf = (GLB R*)S.g;
+          gf[cell] = gix;
+          gf[nc + cell] = giy;
+          gf[2 * nc + cell] = giz;
+          continue;
+        }
+        if (S.has_ib) *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
+        // collision, Eq. (1), (2), (4), in offset form h = f - w
+        const R usq = ux * ux + uy * uy + uz * uz;
+        const R ug = ux * gx + uy * gy + uz * gz;
 #pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      drho += h[q];
-      if (kCx[q]) jx += kCx[q] > 0 ? h[q] : -h[q];
-      if (kCy[q]) jy += kCy[q] > 0 ? h[q] : -h[q];
-      if (kCz[q]) jz += kCz[q] > 0 ? h[q] : -h[q];
-    }
-    R gx = (R)S.gb[0], gy = (R)S.gb[1], gz = (R)S.gb[2];
-    if (S.has_ib) {
-      const GLB R* gf = (const GLB R*)S.g;
-      gx += gf[cell];
-      gy += gf[nc + cell];
-      gz += gf[2 * nc + cell];
-    }
-    const R rho = (R)1 + drho;
-    const R irho = (R)1 / rho;
-    const R ux = (jx + (R)0.5 * gx) * irho;
-    const R uy = (jy + (R)0.5 * gy) * irho;
-    const R uz = (jz + (R)0.5 * gz) * irho;
-    if (mode == 1) {
-      GLB R* rf = (GLB R*)S.rho;
-      rf[cell] = rho;
-      *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
-      continue;
-    }
-    if (S.has_ib) *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
-    // collision, Eq. (1), (2), (4), in offset form h = f - w
-    const R om = (R)(1.0 / S.tau);
-    const R pre = (R)(1.0 - 0.5 / S.tau);
-    const R usq = ux * ux + uy * uy + uz * uz;
-    const R ug = ux * gx + uy * gy + uz * gz;
-    GLB T* dst = (GLB T*)S.f[par ^ 1];
-    const int wx = S.wall[0], wy = S.wall[1], wz = S.wall[2];
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      const R w = (R)wq(q);
-      const R cu = (R)kCx[q] * ux + (R)kCy[q] * uy + (R)kCz[q] * uz;
-      const R cg = (R)kCx[q] * gx + (R)kCy[q] * gy + (R)kCz[q] * gz;
-      // f_eq - w = w (drho + rho (3 cu + 9/2 cu^2 - 3/2 u^2))
-      const R heq = w * (drho + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq));
-      const R Fq = pre * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
-      const R hs = h[q] - om * (h[q] - heq) + Fq;
-      // push to x + c_q
-      int xn = x + kCx[q], yn = y + kCy[q], zn = z + kCz[q];
-      if (!wx) xn = xn < 0 ? xn + nx : (xn >= nx ? xn - nx : xn);
-      if (!wy) yn = yn < 0 ? yn + ny : (yn >= ny ? yn - ny : yn);
-      if (!wz) zn = zn < 0 ? zn + nz : (zn >= nz ? zn - nz : zn);
-      const bool sx = wx && (xn == 0 || xn == nx - 1);
-      const bool sy = wy && (yn == 0 || yn == ny - 1);
-      const bool sz = wz && (zn == 0 || zn == nz - 1);
-      if (q != 0 && (sx || sy || sz)) {
-        // halfway bounce-back off the wall layer of the first wall axis hit
-        const int a = sx ? 0 : (sy ? 1 : 2);
-        const int cn = a == 0 ? xn : (a == 1 ? yn : zn);
-        const double* uw = cn == 0 ? S.ulo[a] : S.uhi[a];
-        const R cuw = (R)(kCx[q] * uw[0] + kCy[q] * uw[1] + kCz[q] * uw[2]);
-        Store<ST>::put(dst, (int64_t)opp(q) * nc + cell, opp(q), hs - (R)6 * w * cuw);
-      } else {
-        const int64_t dn = xn + (int64_t)nx * (yn + (int64_t)ny * zn);
-        Store<ST>::put(dst, (int64_t)q * nc + dn, q, hs);
+        for (int q = 0; q < kQ; ++q) {
+          const R w = (R)wq(q);
+          const R cu = (R)kCx[q] * ux + (R)kCy[q] * uy + (R)kCz[q] * uz;
+          const R cg = (R)kCx[q] * gx + (R)kCy[q] * gy + (R)kCz[q] * gz;
+          // f_eq - w = w (drho + rho (3 cu + 9/2 cu^2 - 3/2 u^2))
+          const R heq = w * (drho + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq));
+          const R Fq = pre * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
+          // post-collision value, stored in place; the next step pulls it
+          Store<ST>::put(dst, (int64_t)q * nc + cell, q, h[q] - om * (h[q] - heq) + Fq);
+        }
       }
     }
+    if (ib) __syncthreads();  // the next brick clears the field
   }
 }
 
@@ -251,8 +400,10 @@ __global__ __launch_bounds__(256) void k_reduce(const SimDev* __restrict__ sims,
       const int z = (int)(t / S.n[1]);
       if (solid_cell(S, x, y, z)) continue;
       double dr = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+      RealOf<ST> hp[kQ];
+      pull_cell<ST>(S, f, x, y, z, cell, hp);
       for (int q = 0; q < kQ; ++q) {
-        const double hq = Store<ST>::hd(f, (int64_t)q * S.ncell + cell, q);
+        const double hq = (double)hp[q];
         dr += hq;
         jx += kCx[q] * hq;
         jy += kCy[q] * hq;
@@ -313,9 +464,9 @@ int grid_for(int items, int cap) {
 hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int profile, hipStream_t s) {
   if (it.lat_total <= 0) return hipSuccess;
   const int grid = grid_for(it.lat_total, 1 << 20);
-  if (storage == kF64) hipLaunchKernelGGL(k_init<kF64>, dim3(grid), dim3(kLatticeBlock), 0, s, sims, it, profile);
-  else if (storage == kF32) hipLaunchKernelGGL(k_init<kF32>, dim3(grid), dim3(kLatticeBlock), 0, s, sims, it, profile);
-  else hipLaunchKernelGGL(k_init<kF16>, dim3(grid), dim3(kLatticeBlock), 0, s, sims, it, profile);
+  if (storage == kF64) hipLaunchKernelGGL(k_init<kF64>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
+  else if (storage == kF32) hipLaunchKernelGGL(k_init<kF32>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
+  else hipLaunchKernelGGL(k_init<kF16>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
   return hipGetLastError();
 }
 
@@ -332,11 +483,9 @@ static void phase_impl(const SimDev* sims, const Items& it, int phase, int mode,
     case kPhaseForces:
       launch_forces(ST, sims, it, mode, s);
       break;
-    case kPhaseSpread:
-      launch_spread(ST, sims, it, mode, s);
-      break;
     case kPhaseLattice:
-      hipLaunchKernelGGL(k_lattice<ST>, dim3(grid_for(it.lat_total, 1 << 22)), dim3(kLatticeBlock), 0, s, sims, it, mode);
+      hipLaunchKernelGGL(k_lattice<ST>, dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s, sims, it,
+                         mode);
       break;
     case kPhaseInterp:
       launch_interp(ST, sims, it, mode, s);

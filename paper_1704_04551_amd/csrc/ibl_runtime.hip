@@ -42,6 +42,27 @@ constexpr int kGraphSteps = 16;
 
 // Force-kernel variant (tuning knob; IBL_FORCES=split selects the edge / node
 // split for every template, the default is one LDS workgroup per capsule).
+// Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x kBrickZ cells,
+// bs[0] the widest of 64, 32, 16 that the x extent fills (long x rows keep
+// the streaming accesses in whole cache lines).  IBL_BRICK_X=16|32|64
+// overrides the choice (tuning).
+void brick_shape(const ibl_sim_desc* d, int bs[3]) {
+  int bx = d->n[0] >= 64 ? 64 : (d->n[0] >= 32 ? 32 : 16);
+  if (const char* v = getenv("IBL_BRICK_X")) {
+    const int t = atoi(v);
+    if (t == 16 || t == 32 || t == 64) bx = t;
+  }
+  bs[0] = bx;
+  bs[1] = kBrickThreads / bx;
+  bs[2] = kBrickZ;
+}
+
+int log2i(int v) {
+  int k = 0;
+  while ((1 << k) < v) ++k;
+  return k;
+}
+
 int forces_variant() {
   const char* v = getenv("IBL_FORCES");
   return (v && strcmp(v, "split") == 0) ? 1 : 0;
@@ -77,8 +98,10 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||
       d->max_template_edges < 0)
     return fail(IBL_ERR_ARG, "negative capacity");
-  if (ceil_div((int64_t)d->n[0] * d->n[1] * d->n[2], kLatticeBlock) >= (int64_t)1 << 31)
-    return fail(IBL_ERR_ARG, "lattice too large");
+  // streaming addresses two population planes with 32-bit byte offsets
+  if ((d->storage == 0 || d->storage == 1 || d->storage == 2) &&
+      2 * (int64_t)d->n[0] * d->n[1] * d->n[2] * storage_bytes(d->storage) >= ((int64_t)1 << 32))
+    return fail(IBL_ERR_ARG, "lattice too large for its storage (2 ncell x element bytes must stay below 4 GiB)");
   if (d->max_nodes >= (1 << 26)) return fail(IBL_ERR_ARG, "at most 2^26 - 1 nodes per simulation");
   for (int a = 0; a < 3; ++a)
     for (int c = 0; c < 3; ++c)
@@ -91,8 +114,10 @@ Layout make_layout(const ibl_sim_desc* d) {
   Layout L;
   const int st = d->storage;
   const int64_t ncell = (int64_t)d->n[0] * d->n[1] * d->n[2];
+  int bs[3];
+  brick_shape(d, bs);
   int64_t nb = 1;
-  for (int a = 0; a < 3; ++a) nb *= ceil_div(d->n[a], kBrick);
+  for (int a = 0; a < 3; ++a) nb *= ceil_div(d->n[a], bs[a]);
   const bool ib = d->max_nodes > 0;
   L.ncell = ncell;
   L.nbrick = nb;
@@ -138,7 +163,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.red = take((size_t)L.nred * 4 * 8);
   L.red_out = take(4 * 8);
   L.simdev = take(sizeof(SimDev));
-  L.items = take(10 * 4);
+  L.items = take(8 * 4);
   L.total = o;
   return L;
 }
@@ -243,17 +268,15 @@ ibl_status upload_simdev(ibl_sim S) {
   S->hd.nnodes = S->nnodes;
   S->hd.nmeshes = S->nmesh;
   S->hd.has_ib = S->nmesh > 0 ? 1 : 0;
-  int32_t h[10];
+  int32_t h[8];
   h[0] = 0;
-  h[1] = (int32_t)ceil_div(S->L.ncell, kLatticeBlock);
+  h[1] = (int32_t)S->L.nbrick;
   h[2] = 0;
   h[3] = (int32_t)S->L.nred;
   h[4] = 0;
   h[5] = S->nmesh;
   h[6] = 0;
   h[7] = S->nmesh > 0 ? (int32_t)S->L.nbrick : 0;
-  h[8] = 0;
-  h[9] = (int32_t)ceil_div(S->nnodes, kNodesPerItem);
   HIPCHK(hipMemcpyAsync(S->dd, &S->hd, sizeof(SimDev), hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(S->ditems, h, sizeof(h), hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipStreamSynchronize(S->stream));
@@ -263,12 +286,10 @@ ibl_status upload_simdev(ibl_sim S) {
   it.red_total = h[3];
   it.mesh_total = h[5];
   it.brick_total = h[7];
-  it.node_total = h[9];
   it.lat_off = S->ditems + 0;
   it.red_off = S->ditems + 2;
   it.mesh_off = S->ditems + 4;
   it.brick_off = S->ditems + 6;
-  it.node_off = S->ditems + 8;
   it.big_templates = S->big_templates;
   it.forces_variant = forces_variant();
   drop_graphs(S->g1, S->gN);
@@ -330,16 +351,26 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   char* A = S->arena;
   SimDev& d = S->hd;
   memset(&d, 0, sizeof(d));
+  int bs[3];
+  brick_shape(desc, bs);
   for (int a = 0; a < 3; ++a) {
     d.n[a] = desc->n[a];
     d.wall[a] = desc->wall[a];
-    d.nb[a] = (int32_t)ceil_div(desc->n[a], kBrick);
+    d.nb[a] = (int32_t)ceil_div(desc->n[a], bs[a]);
+    d.bs[a] = bs[a];
+    d.bsh[a] = log2i(bs[a]);
     d.gb[a] = desc->g_body[a];
     for (int c = 0; c < 3; ++c) {
       d.ulo[a][c] = desc->wall_u_lo[a][c];
       d.uhi[a][c] = desc->wall_u_hi[a][c];
     }
   }
+  for (int q = 0; q < kQ; ++q)
+    for (int a = 0; a < 3; ++a)
+      for (int hi = 0; hi < 2; ++hi) {
+        const double* uw = hi ? d.uhi[a] : d.ulo[a];
+        d.bbw[q][2 * a + hi] = 6.0 * wq(q) * (kCx[q] * uw[0] + kCy[q] * uw[1] + kCz[q] * uw[2]);
+      }
   d.ncell = L.ncell;
   d.nbrick = L.nbrick;
   d.delta = desc->delta;
@@ -776,13 +807,12 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   B->storage = sims[0]->desc.storage;
   B->stream = sims[0]->stream;
   std::vector<SimDev> host(n);
-  std::vector<int32_t> offs(5 * (size_t)(n + 1));
+  std::vector<int32_t> offs(4 * (size_t)(n + 1));
   int32_t* lat = offs.data();
   int32_t* red = lat + (n + 1);
   int32_t* msh = red + (n + 1);
   int32_t* brk = msh + (n + 1);
-  int32_t* nod = brk + (n + 1);
-  lat[0] = red[0] = msh[0] = brk[0] = nod[0] = 0;
+  lat[0] = red[0] = msh[0] = brk[0] = 0;
   for (int i = 0; i < n; ++i) {
     const Items& it = sims[i]->items;
     host[i] = sims[i]->hd;
@@ -790,7 +820,6 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
     red[i + 1] = red[i] + it.red_total;
     msh[i + 1] = msh[i] + it.mesh_total;
     brk[i + 1] = brk[i] + it.brick_total;
-    nod[i + 1] = nod[i] + it.node_total;
   }
   hipError_t e = hipMalloc(&B->dsims, sizeof(SimDev) * n);
   if (!e) e = hipMalloc(&B->doffs, offs.size() * 4);
@@ -809,12 +838,10 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.red_total = red[n];
   it.mesh_total = msh[n];
   it.brick_total = brk[n];
-  it.node_total = nod[n];
   it.lat_off = B->doffs;
   it.red_off = B->doffs + (n + 1);
   it.mesh_off = B->doffs + 2 * (n + 1);
   it.brick_off = B->doffs + 3 * (n + 1);
-  it.node_off = B->doffs + 4 * (n + 1);
   it.big_templates = 0;
   for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
   it.forces_variant = forces_variant();

@@ -223,14 +223,14 @@ class Sim:
             _check(st)
         return float(m[0]), p, int(h[0])
 
-    PHASES = ("forces", "spread", "lattice", "interp", "advance")
+    PHASES = ("forces", "lattice", "interp", "advance")
 
     def profile_phases(self, n):
         """Run n steps phase by phase with HIP events; returns
         ({phase: mean ms per step}, total ms)."""
-        ms = np.zeros(6)
+        ms = np.zeros(len(self.PHASES) + 1)
         _check(lib().ibl_profile_phases(self.h, int(n), _p(ms)))
-        return dict(zip(self.PHASES, ms[:5].tolist())), float(ms[5])
+        return dict(zip(self.PHASES, ms[:-1].tolist())), float(ms[-1])
 
     def read_state(self) -> bytes:
         nb = ctypes.c_size_t()
