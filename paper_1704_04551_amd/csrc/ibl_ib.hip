@@ -11,10 +11,10 @@
 //                 base, delta weights, F) and appends the node to the
 //                 candidate lists of the lattice bricks its 4x4x4 stencil
 //                 touches.
-//   k_interp      Eq. (14): one workgroup per brick, the brick's velocity and
-//                 its stencil margin in LDS, one lane per home node, fixed
-//                 summation order; X^{n+1} = X^n + U (FP64).  Clears the
-//                 brick's candidate list.
+//   k_interp      Eq. (14): one workgroup per home cube (16 x 16 x 8 cells),
+//                 the cube's velocity and its stencil margin in LDS, one lane
+//                 per home node, fixed summation order; X^{n+1} = X^n + U
+//                 (FP64).  Clears the cube's node list.
 // Force spreading (Eq. (15)) runs per brick inside the collide-stream kernel
 // (ibl_kernels.hip), from the candidate lists written here.
 #include "ibl_device.h"
@@ -396,31 +396,27 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
 }
 
 // --------------------------------------------------------------- interp --
-// Eq. (14) per brick.  Every valid node has one home brick, the brick of its
-// base cell, and is on that brick's candidate list.  The workgroup of a brick
-// loads the velocity of the brick and of the stencil margin around it (cells
-// o-1 .. o+size+1 per axis; solid cells hold their wall's velocity) into LDS;
-// each lane takes one candidate and, if the brick is its home, sums its 64
-// stencil points in a fixed order: the result does not depend on the list's
-// order.  X^{n+1} = X^n + U in FP64.  The workgroup also clears the brick's
-// list for the next step's appends.
+// Eq. (14) per home cube (16 x 16 x 8 cells): the workgroup loads the
+// velocity of the cube and of the stencil margin around it (cells o-1 ..
+// o+size+1 per axis; solid cells hold their wall's velocity) into LDS, and
+// each lane sums one home node's 64 stencil points in a fixed order: the
+// result does not depend on the list's order.  X^{n+1} = X^n + U in FP64.
+// The workgroup also clears the cube's list for the next step's appends.
 constexpr int kInterpThreads = 256;
-// largest margin tile over the brick shapes (64 x 4 x 4 -> 67 x 7 x 7)
-constexpr int kTileMax = (64 + 3) * (kBrickThreads / 64 + 3) * (kBrickZ + 3);
-static_assert((32 + 3) * (kBrickThreads / 32 + 3) * (kBrickZ + 3) <= kTileMax, "tile size");
-static_assert((16 + 3) * (kBrickThreads / 16 + 3) * (kBrickZ + 3) <= kTileMax, "tile size");
+constexpr int kCubeTile = ((1 << kCubeShift[0]) + 3) * ((1 << kCubeShift[1]) + 3) * ((1 << kCubeShift[2]) + 3);
 
 __device__ __forceinline__ int margin_wrap(int c, int n) {
-  // the margin spans -1 .. n + 63 + 2; for an axis shorter than the brick the
-  // tile may wrap several times
+  // the margin spans -1 .. n + 17; an axis shorter than the cube may need
+  // several turns
   c = c < 0 ? c + n : c;
   while (c >= n) c -= n;
   return c;
 }
 
 template <typename R>
-__device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kTileMax], const NodeRec<R>& q,
-                                            int node, int ox, int oy, int oz, int ex, int exy, int mode) {
+__device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCubeTile], const NodeRec<R>& q,
+                                            int node, int ox, int oy, int oz, int mode) {
+  constexpr int ex = (1 << kCubeShift[0]) + 3, exy = ex * ((1 << kCubeShift[1]) + 3);
   // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
   const int t0 = (q.base[0] - ox) + ex * (q.base[1] - oy) + exy * (q.base[2] - oz);
   R sx = (R)0, sy = (R)0, sz = (R)0;
@@ -453,26 +449,27 @@ __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kTile
 template <typename R>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restrict__ sims, Items it,
                                                            int mode) {
-  __shared__ R ut[3][kTileMax];
+  __shared__ R ut[3][kCubeTile];
+  constexpr int ex = (1 << kCubeShift[0]) + 3, exy = ex * ((1 << kCubeShift[1]) + 3);
   const int tid = threadIdx.x;
-  for (int item = xcd_block(); item < it.brick_total; item += gridDim.x) {
-    const int s = find_sim(it.brick_off, it.nsim, item);
+  for (int item = xcd_block(); item < it.cube_total; item += gridDim.x) {
+    const int s = find_sim(it.cube_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
-    const int64_t b = item - it.brick_off[s];
-    int cnt = S.bcount[b];
-    if (cnt == 0) continue;  // no node near this brick (uniform)
-    cnt = cnt > kCandCap ? kCandCap : cnt;
+    const int64_t h = item - it.cube_off[s];
+    int cnt = S.hcount[h];
+    if (cnt == 0) continue;  // no node has its base here (uniform)
+    if (tid == 0 && cnt > kHomeCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
+    cnt = cnt > kHomeCap ? kHomeCap : cnt;
     const int n0 = S.n[0], n1 = S.n[1], n2 = S.n[2];
     const int w0 = S.wall[0], w1 = S.wall[1], w2 = S.wall[2];
-    int ox, oy, oz;
-    brick_origin(S, b, ox, oy, oz);
-    const int ex = S.bs[0] + 3, ey = S.bs[1] + 3, exy = ex * ey, ncells = exy * (S.bs[2] + 3);
-    const int bx = S.bs[0], by = S.bs[1], bz = S.bs[2];
+    const int64_t r = h / S.nq[0];
+    const int ox = (int)(h - r * S.nq[0]) << kCubeShift[0];
+    const int oy = (int)(r % S.nq[1]) << kCubeShift[1];
+    const int oz = (int)(r / S.nq[1]) << kCubeShift[2];
     const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
-    const GLB int32_t* list = S.blist + b * kCandCap;
-    // this lane's first candidate, fetched before the tile so both are in
-    // flight together
+    const GLB int32_t* list = S.hlist + h * kHomeCap;
+    // this lane's first node, fetched before the tile so both are in flight
     int node = -1;
     NodeRec<R> q;
     if (tid < cnt) {
@@ -480,8 +477,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       q = *(const NodeRec<R>*)(rec + node);
     }
     const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
-    for (int t = tid; t < ncells; t += blockDim.x) {
-      const int tz = t / exy, r = t - tz * exy, ty = r / ex, tx = r - ty * ex;
+    for (int t = tid; t < kCubeTile; t += blockDim.x) {
+      const int tz = t / exy, rr = t - tz * exy, ty = rr / ex, tx = rr - ty * ex;
       const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
       const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
       const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
@@ -498,7 +495,6 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       ut[2][t] = vz;
     }
     __syncthreads();
-    // one lane per candidate; a node is interpolated by its home brick only
     for (int i0 = 0; i0 < cnt; i0 += blockDim.x) {
       if (i0 > 0) {
         node = -1;
@@ -507,15 +503,10 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
           q = *(const NodeRec<R>*)(rec + node);
         }
       }
-      if (node >= 0 && (unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
-          (unsigned)(q.base[2] - oz) < (unsigned)bz)
-        interp_node<R>(S, ut, q, node, ox, oy, oz, ex, exy, mode);
+      if (node >= 0) interp_node<R>(S, ut, q, node, ox, oy, oz, mode);
     }
     __syncthreads();
-    if (tid == 0) {
-      S.bcount[b] = 0;
-      S.bmax[b] = 0u;
-    }
+    if (tid == 0) S.hcount[h] = 0;
   }
 }
 
@@ -547,8 +538,8 @@ void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, h
 }
 
 void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
-  if (it.mesh_total <= 0 || it.brick_total <= 0) return;
-  const dim3 grid(grid_for(it.brick_total, 1 << 20)), block(kInterpThreads);
+  if (it.mesh_total <= 0 || it.cube_total <= 0) return;
+  const dim3 grid(grid_for(it.cube_total, 1 << 20)), block(kInterpThreads);
   if (storage == kF64) hipLaunchKernelGGL(k_interp<double>, grid, block, 0, s, sims, it, mode);
   else hipLaunchKernelGGL(k_interp<float>, grid, block, 0, s, sims, it, mode);
 }

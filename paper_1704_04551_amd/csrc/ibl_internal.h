@@ -26,6 +26,10 @@ constexpr int kBrickThreads = 256;
 constexpr int kBrickZ = 4;
 constexpr int kBrickCells = kBrickThreads * kBrickZ;
 constexpr int kCandCap = 4096;       // candidate nodes per brick
+// Interpolation groups nodes by home cube (the cube of their stencil base
+// cell), cubes of kCube[0] x kCube[1] x kCube[2] cells.
+constexpr int kCubeShift[3] = {4, 4, 3};
+constexpr int kHomeCap = 4096;       // nodes per home cube
 constexpr int kLatticeBlock = 256;   // threads of the reduction work items
 constexpr int kLdsNodes = 642;       // template size handled by the LDS force kernel (icosphere level 3)
 constexpr int kLdsEdges = 1920;
@@ -79,6 +83,8 @@ struct SimDev {
   int32_t bsh[3];         // log2 of bs
   int32_t delta;
   int64_t nbrick;
+  int32_t nq[3];          // home cubes per axis
+  int64_t ncube;
   double tau;
   double gb[3];
   double ulo[3][3];
@@ -102,6 +108,8 @@ struct SimDev {
   IBL_G(int32_t) bcount;        // [nbrick]
   IBL_G(uint32_t) bmax;         // [nbrick] largest |F component| among the brick's candidates (float bits)
   IBL_G(int32_t) blist;         // [nbrick][kCandCap]
+  IBL_G(int32_t) hcount;        // [ncube] nodes per home cube
+  IBL_G(int32_t) hlist;         // [ncube][kHomeCap]
   // meshes
   IBL_G(int32_t) mesh_tmpl;     // [max_meshes]
   IBL_G(int32_t) mesh_off;      // [max_meshes] first global node
@@ -132,13 +140,13 @@ struct Items {
   int32_t lat_total;         // bricks (every simulation)
   int32_t red_total;         // reduction items
   int32_t mesh_total;        // capsules
-  int32_t brick_total;       // bricks of simulations with capsules (interpolation)
+  int32_t cube_total;        // home cubes of simulations with capsules (interpolation) (interpolation)
   int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
   int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;
-  const int32_t* brick_off;
+  const int32_t* cube_off;
 };
 
 // Phases of one timestep, in launch order.

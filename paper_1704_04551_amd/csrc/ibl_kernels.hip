@@ -156,7 +156,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     const int s = find_sim(it.lat_off, it.nsim, item);
     const SimDev& S = sims[s];
     const int64_t b = item - it.lat_off[s];
-    if (tid == 0) {  // the arena may hold a previous user's data
+    // the arena may hold a previous user's data: every list is emptied
+    for (int64_t j = b * kBrickThreads + tid; j < S.ncube; j += S.nbrick * kBrickThreads) S.hcount[j] = 0;
+    if (tid == 0) {
       S.bcount[b] = 0;
       S.bmax[b] = 0u;
       if (b == 0) {
@@ -227,6 +229,10 @@ __global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restr
   using FA = FixAcc<R>;
   using A = typename FA::A;
   __shared__ A gq[3][kBrickCells];
+  // home-cube lists: the brick's home candidates (base cell inside the brick)
+  // counted per cube (the brick meets bx / 16 <= 4 cubes, along x only)
+  __shared__ int hc[4], hb[4];
+  __shared__ uint16_t hr[kCandCap];  // (local cube << 12) | rank, or 0xffff
   const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.lat_total; item += gridDim.x) {
     const int s = find_sim(it.lat_off, it.nsim, item);
@@ -253,6 +259,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restr
 #pragma unroll
       for (int k = 0; k < kBrickZ; ++k) gq[0][tid + kBrickThreads * k] = gq[1][tid + kBrickThreads * k] =
           gq[2][tid + kBrickThreads * k] = (A)0;
+      if (tid < 4) hc[tid] = 0;
       __syncthreads();
       int e2;
       frexpf(__uint_as_float(fmx), &e2);
@@ -262,6 +269,14 @@ __global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restr
       inv = (R)ldexp(1.0, -sh);
       for (int i = tid; i < cnt; i += blockDim.x) {
         if (i != tid) q = *(const NodeRec<R>*)(rec + list[i]);
+        // a node is interpolated through its home cube's list (one entry per node)
+        uint16_t hrank = 0xffffu;
+        if ((unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
+            (unsigned)(q.base[2] - oz) < (unsigned)bz) {
+          const int lc = (q.base[0] >> kCubeShift[0]) - (ox >> kCubeShift[0]);
+          hrank = (uint16_t)((lc << 12) | atomicAdd(&hc[lc], 1));
+        }
+        hr[i] = hrank;
         int lx[4], ly[4], lz[4], mx, my, mz;
         axis_cells(q.base[0], ox, nx, S.wall[0], bx, lx, mx);
         axis_cells(q.base[1], oy, ny, S.wall[1], by, ly, my);
@@ -289,6 +304,20 @@ __global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restr
         }
       }
       __syncthreads();
+      // home cubes: one global reservation per (brick, cube), then the entries
+      const int cube0 = (ox >> kCubeShift[0]) + S.nq[0] * ((oy >> kCubeShift[1]) + S.nq[1] * (oz >> kCubeShift[2]));
+      if (tid < 4 && hc[tid] > 0) hb[tid] = atomicAdd((int*)&S.hcount[cube0 + tid], hc[tid]);
+      __syncthreads();
+      for (int i = tid; i < cnt; i += blockDim.x) {
+        const uint16_t v = hr[i];
+        if (v == 0xffffu) continue;
+        const int lc = v >> 12, pos = hb[lc] + (v & 0xfff);
+        if (pos < kHomeCap) S.hlist[(int64_t)(cube0 + lc) * kHomeCap + pos] = list[i];
+      }
+      if (tid == 0) {  // every lane has read the list: the next step rebuilds it
+        S.bcount[b] = 0;
+        S.bmax[b] = 0u;
+      }
     }
     // ---- collide-stream, a column of kBrickZ cells per thread
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);

@@ -77,12 +77,12 @@ size_t rec_bytes(int st) { return st == kF64 ? sizeof(NodeRec<double>) : sizeof(
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
-  size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, bmax, blist;
+  size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, bmax, blist, hcount, hlist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
   size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0, txref;
   size_t step, remaining, health, red, red_out, simdev, items;
   size_t total;
-  int64_t ncell, nbrick, nred;
+  int64_t ncell, nbrick, ncube, nred;
 };
 
 ibl_status check_desc(const ibl_sim_desc* d) {
@@ -119,8 +119,11 @@ Layout make_layout(const ibl_sim_desc* d) {
   int64_t nb = 1;
   for (int a = 0; a < 3; ++a) nb *= ceil_div(d->n[a], bs[a]);
   const bool ib = d->max_nodes > 0;
+  int64_t nq = 1;
+  for (int a = 0; a < 3; ++a) nq *= ceil_div(d->n[a], 1 << kCubeShift[a]);
   L.ncell = ncell;
   L.nbrick = nb;
+  L.ncube = nq;
   L.nred = ceil_div(ncell, kReduceItemCells);
   const size_t maxn = (size_t)d->max_nodes;
   size_t o = 0;
@@ -142,6 +145,8 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.bcount = take((size_t)nb * 4);
   L.bmax = take((size_t)nb * 4);
   L.blist = take(ib ? (size_t)nb * kCandCap * 4 : 4);
+  L.hcount = take((size_t)nq * 4);
+  L.hlist = take(ib ? (size_t)nq * kHomeCap * 4 : 4);
   L.mesh_tmpl = take((size_t)d->max_meshes * 4);
   L.mesh_off = take((size_t)d->max_meshes * 4);
   L.mesh_ks = take((size_t)d->max_meshes * 8);
@@ -276,7 +281,7 @@ ibl_status upload_simdev(ibl_sim S) {
   h[4] = 0;
   h[5] = S->nmesh;
   h[6] = 0;
-  h[7] = S->nmesh > 0 ? (int32_t)S->L.nbrick : 0;
+  h[7] = S->nmesh > 0 ? (int32_t)S->L.ncube : 0;
   HIPCHK(hipMemcpyAsync(S->dd, &S->hd, sizeof(SimDev), hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(S->ditems, h, sizeof(h), hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipStreamSynchronize(S->stream));
@@ -285,11 +290,11 @@ ibl_status upload_simdev(ibl_sim S) {
   it.lat_total = h[1];
   it.red_total = h[3];
   it.mesh_total = h[5];
-  it.brick_total = h[7];
+  it.cube_total = h[7];
   it.lat_off = S->ditems + 0;
   it.red_off = S->ditems + 2;
   it.mesh_off = S->ditems + 4;
-  it.brick_off = S->ditems + 6;
+  it.cube_off = S->ditems + 6;
   it.big_templates = S->big_templates;
   it.forces_variant = forces_variant();
   drop_graphs(S->g1, S->gN);
@@ -389,6 +394,10 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.bcount = (int32_t*)(A + L.bcount);
   d.bmax = (uint32_t*)(A + L.bmax);
   d.blist = (int32_t*)(A + L.blist);
+  d.hcount = (int32_t*)(A + L.hcount);
+  d.hlist = (int32_t*)(A + L.hlist);
+  d.ncube = L.ncube;
+  for (int a = 0; a < 3; ++a) d.nq[a] = (int32_t)ceil_div(desc->n[a], 1 << kCubeShift[a]);
   d.mesh_tmpl = (int32_t*)(A + L.mesh_tmpl);
   d.mesh_off = (int32_t*)(A + L.mesh_off);
   d.mesh_ks = (double*)(A + L.mesh_ks);
@@ -819,7 +828,7 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
     lat[i + 1] = lat[i] + it.lat_total;
     red[i + 1] = red[i] + it.red_total;
     msh[i + 1] = msh[i] + it.mesh_total;
-    brk[i + 1] = brk[i] + it.brick_total;
+    brk[i + 1] = brk[i] + it.cube_total;
   }
   hipError_t e = hipMalloc(&B->dsims, sizeof(SimDev) * n);
   if (!e) e = hipMalloc(&B->doffs, offs.size() * 4);
@@ -837,11 +846,11 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.lat_total = lat[n];
   it.red_total = red[n];
   it.mesh_total = msh[n];
-  it.brick_total = brk[n];
+  it.cube_total = brk[n];
   it.lat_off = B->doffs;
   it.red_off = B->doffs + (n + 1);
   it.mesh_off = B->doffs + 2 * (n + 1);
-  it.brick_off = B->doffs + 3 * (n + 1);
+  it.cube_off = B->doffs + 3 * (n + 1);
   it.big_templates = 0;
   for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
   it.forces_variant = forces_variant();
