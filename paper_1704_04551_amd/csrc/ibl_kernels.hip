@@ -221,8 +221,9 @@ struct FixAcc<double> {
   __device__ static void add(A* p, A v) { atomicAdd((unsigned long long*)p, (unsigned long long)v); }
 };
 
+// FP32 / FP16: registers capped for 5 waves per SIMD (measured best; 6 spills)
 template <int ST>
-__global__ __launch_bounds__(kBrickThreads) void k_lattice(const SimDev* __restrict__ sims,
+__global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
