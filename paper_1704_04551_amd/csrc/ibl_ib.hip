@@ -11,7 +11,7 @@
 //                 base, delta weights, F) and appends the node to the
 //                 candidate lists of the lattice bricks its 4x4x4 stencil
 //                 touches.
-//   k_interp      Eq. (14): one workgroup per home cube (16 x 16 x 8 cells),
+//   k_interp      Eq. (14): one workgroup per home cube (16 x 8 x 8 cells),
 //                 the cube's velocity and its stencil margin in LDS, one lane
 //                 per home node, fixed summation order; X^{n+1} = X^n + U
 //                 (FP64).  Clears the cube's node list.
@@ -396,7 +396,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
 }
 
 // --------------------------------------------------------------- interp --
-// Eq. (14) per home cube (16 x 16 x 8 cells): the workgroup loads the
+// Eq. (14) per home cube (16 x 8 x 8 cells): the workgroup loads the
 // velocity of the cube and of the stencil margin around it (cells o-1 ..
 // o+size+1 per axis; solid cells hold their wall's velocity) into LDS, and
 // each lane sums one home node's 64 stencil points in a fixed order: the
@@ -406,7 +406,7 @@ constexpr int kInterpThreads = 256;
 constexpr int kCubeTile = ((1 << kCubeShift[0]) + 3) * ((1 << kCubeShift[1]) + 3) * ((1 << kCubeShift[2]) + 3);
 
 __device__ __forceinline__ int margin_wrap(int c, int n) {
-  // the margin spans -1 .. n + 17; an axis shorter than the cube may need
+  // the margin spans -1 .. n + 17 at most; an axis shorter than the cube may need
   // several turns
   c = c < 0 ? c + n : c;
   while (c >= n) c -= n;

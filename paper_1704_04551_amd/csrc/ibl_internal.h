@@ -28,7 +28,7 @@ constexpr int kBrickCells = kBrickThreads * kBrickZ;
 constexpr int kCandCap = 4096;       // candidate nodes per brick
 // Interpolation groups nodes by home cube (the cube of their stencil base
 // cell), cubes of kCube[0] x kCube[1] x kCube[2] cells.
-constexpr int kCubeShift[3] = {4, 4, 3};
+constexpr int kCubeShift[3] = {4, 3, 3};
 constexpr int kHomeCap = 4096;       // nodes per home cube
 constexpr int kLatticeBlock = 256;   // threads of the reduction work items
 constexpr int kLdsNodes = 642;       // template size handled by the LDS force kernel (icosphere level 3)

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
   using A = typename FA::A;
   __shared__ A gq[3][kBrickCells];
   // home-cube lists: the brick's home candidates (base cell inside the brick)
-  // counted per cube (the brick meets bx / 16 <= 4 cubes, along x only)
+  // counted per cube (a brick meets at most 4 cubes: 64 x 4 -> 4 x 1,
+  // 32 x 8 -> 2 x 1, 16 x 16 -> 1 x 2)
   __shared__ int hc[4], hb[4];
   __shared__ uint16_t hr[kCandCap];  // (local cube << 12) | rank, or 0xffff
   const int tid = threadIdx.x;
@@ -261,6 +262,8 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       for (int k = 0; k < kBrickZ; ++k) gq[0][tid + kBrickThreads * k] = gq[1][tid + kBrickThreads * k] =
           gq[2][tid + kBrickThreads * k] = (A)0;
       if (tid < 4) hc[tid] = 0;
+      // cubes the brick meets: nlx along x by (at most 2) along y
+      const int nlx = bx >> kCubeShift[0] > 0 ? bx >> kCubeShift[0] : 1;
       __syncthreads();
       int e2;
       frexpf(__uint_as_float(fmx), &e2);
@@ -274,7 +277,8 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         uint16_t hrank = 0xffffu;
         if ((unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
             (unsigned)(q.base[2] - oz) < (unsigned)bz) {
-          const int lc = (q.base[0] >> kCubeShift[0]) - (ox >> kCubeShift[0]);
+          const int lc = (q.base[0] >> kCubeShift[0]) - (ox >> kCubeShift[0]) +
+                         nlx * ((q.base[1] >> kCubeShift[1]) - (oy >> kCubeShift[1]));
           hrank = (uint16_t)((lc << 12) | atomicAdd(&hc[lc], 1));
         }
         hr[i] = hrank;
@@ -307,13 +311,15 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       __syncthreads();
       // home cubes: one global reservation per (brick, cube), then the entries
       const int cube0 = (ox >> kCubeShift[0]) + S.nq[0] * ((oy >> kCubeShift[1]) + S.nq[1] * (oz >> kCubeShift[2]));
-      if (tid < 4 && hc[tid] > 0) hb[tid] = atomicAdd((int*)&S.hcount[cube0 + tid], hc[tid]);
+      if (tid < 4 && hc[tid] > 0)
+        hb[tid] = atomicAdd((int*)&S.hcount[cube0 + tid % nlx + S.nq[0] * (tid / nlx)], hc[tid]);
       __syncthreads();
       for (int i = tid; i < cnt; i += blockDim.x) {
         const uint16_t v = hr[i];
         if (v == 0xffffu) continue;
         const int lc = v >> 12, pos = hb[lc] + (v & 0xfff);
-        if (pos < kHomeCap) S.hlist[(int64_t)(cube0 + lc) * kHomeCap + pos] = list[i];
+        const int cube = cube0 + lc % nlx + S.nq[0] * (lc / nlx);
+        if (pos < kHomeCap) S.hlist[(int64_t)cube * kHomeCap + pos] = list[i];
       }
       if (tid == 0) {  // every lane has read the list: the next step rebuilds it
         S.bcount[b] = 0;
