@@ -236,6 +236,20 @@ __device__ __forceinline__ void delta_weights_r<float>(int kind, float d, float 
   }
 }
 
+// The 12 delta weights of a spreading record (stored, or evaluated from the
+// fractional offsets with the same function that the force kernel used).
+__device__ __forceinline__ void rec_weights(const NodeRec<double>& q, int kind, double w[3][4]) {
+  (void)kind;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[a][k] = q.w[a][k];
+}
+__device__ __forceinline__ void rec_weights(const NodeRec<float>& q, int kind, float w[3][4]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) delta_weights_r<float>(kind, q.d[a], w[a]);
+}
+
 template <typename R>
 struct alignas(4 * sizeof(R)) R4 {
   R x, y, z, w;

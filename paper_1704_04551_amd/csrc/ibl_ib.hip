@@ -44,6 +44,33 @@ __device__ __forceinline__ void axis_bricks(int base, int n, int wall, int shift
   }
 }
 
+// Store a node's spreading record (see NodeRec).
+__device__ __forceinline__ void write_record(const SimDev& S, int gid, const int base[3], int valid,
+                                             const double d[3], const double Fv[3]) {
+  NodeRec<double> q;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.base[a] = base[a];
+    delta_weights(S.delta, d[a], q.w[a]);
+    q.F[a] = Fv[a];
+  }
+  q.valid = valid;
+  q.pad = 0.0;
+  *(NodeRec<double>*)((GLB NodeRec<double>*)S.rec + gid) = q;
+}
+__device__ __forceinline__ void write_record(const SimDev& S, int gid, const int base[3], int valid,
+                                             const float d[3], const double Fv[3]) {
+  NodeRec<float> q;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    q.base[a] = (int16_t)base[a];
+    q.d[a] = d[a];
+    q.F[a] = (float)Fv[a];
+  }
+  q.valid = (int16_t)valid;
+  *(NodeRec<float>*)((GLB NodeRec<float>*)S.rec + gid) = q;
+}
+
 // Spreading record and validity check of one node; fills the bricks its
 // stencil touches.
 template <typename R>
@@ -53,7 +80,6 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
   S.F[gid] = Fv[0];
   S.F[ms + gid] = Fv[1];
   S.F[2 * ms + gid] = Fv[2];
-  NodeRec<R> q;
   int valid = 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -65,25 +91,21 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
       atomicOr((unsigned*)S.health, (uint32_t)kHNodeRange);
     }
   }
-  q.valid = valid;
+  int base[3];
+  R d[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const double fb = valid ? floor(Xp[a]) : 0.0;
     // periodic axes: the base cell taken modulo n, so consumers wrap with one compare
-    q.base[a] = S.wall[a] ? (int32_t)fb : wrap((int32_t)(fb - (double)S.n[a] * floor(fb / S.n[a])), S.n[a]);
-    R w[4];
-    delta_weights_r<R>(S.delta, (R)(valid ? Xp[a] - fb : 0.0), w);
-#pragma unroll
-    for (int k = 0; k < 4; ++k) q.w[a][k] = w[k];
-    q.F[a] = (R)Fv[a];
+    base[a] = S.wall[a] ? (int32_t)fb : wrap((int32_t)(fb - (double)S.n[a] * floor(fb / S.n[a])), S.n[a]);
+    d[a] = (R)(valid ? Xp[a] - fb : 0.0);
   }
-  q.pad = (R)0;
-  *(NodeRec<R>*)((GLB NodeRec<R>*)S.rec + gid) = q;
+  write_record(S, gid, base, valid, d, Fv);
   nb.mask = 0;
   nb.rare = 0;
-  nb.base[0] = q.base[0];
-  nb.base[1] = q.base[1];
-  nb.base[2] = q.base[2];
+  nb.base[0] = base[0];
+  nb.base[1] = base[1];
+  nb.base[2] = base[2];
   if (!valid) {  // on no candidate list: interpolation never visits it
     S.U[gid] = 0.0;
     S.U[ms + gid] = 0.0;
@@ -94,7 +116,7 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int b[4];
-    axis_bricks(q.base[a], S.n[a], S.wall[a], S.bsh[a], b);
+    axis_bricks(base[a], S.n[a], S.wall[a], S.bsh[a], b);
     p0[a] = b[0];
     p1[a] = b[1] != b[0] ? b[1] : (b[2] != b[0] ? b[2] : b[3]);
     h1[a] = p1[a] != b[0];
@@ -419,16 +441,18 @@ __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCube
   constexpr int ex = (1 << kCubeShift[0]) + 3, exy = ex * ((1 << kCubeShift[1]) + 3);
   // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
   const int t0 = (q.base[0] - ox) + ex * (q.base[1] - oy) + exy * (q.base[2] - oz);
+  R w3[3][4];
+  rec_weights(q, S.delta, w3);
   R sx = (R)0, sy = (R)0, sz = (R)0;
 #pragma unroll
   for (int dz = 0; dz < 4; ++dz)
 #pragma unroll
     for (int dy = 0; dy < 4; ++dy) {
-      const R wyz = q.w[1][dy] * q.w[2][dz];
+      const R wyz = w3[1][dy] * w3[2][dz];
       const int trow = t0 + ex * dy + exy * dz;
 #pragma unroll
       for (int dx = 0; dx < 4; ++dx) {
-        const R w = q.w[0][dx] * wyz;
+        const R w = w3[0][dx] * wyz;
         sx += w * ut[0][trow + dx];
         sy += w * ut[1][trow + dx];
         sz += w * ut[2][trow + dx];

@@ -62,15 +62,27 @@ enum Health : uint32_t {
 };
 
 // Spreading record of one node, written by the force kernel at X^n and read by
-// the spreading and interpolation kernels of the same step.
+// the spreading and interpolation kernels of the same step.  FP64 storage
+// keeps the 12 delta weights; FP32 / FP16 storage keeps the fractional offset
+// of X from its base cell per axis (32 bytes: each record is read by the ~3
+// bricks its stencil meets, so its size is HBM traffic) and the readers
+// evaluate the same weights from it.
 template <typename R>
 struct alignas(16) NodeRec {
-  int32_t base[3];   // floor(X) per axis (unwrapped)
+  int32_t base[3];   // floor(X) per axis (periodic axes: modulo n)
   int32_t valid;     // 0 when the node is outside the admissible range
   R w[3][4];         // phi at offsets -1, 0, +1, +2 from base, per axis
   R F[3];            // membrane force
   R pad;
 };
+template <>
+struct alignas(16) NodeRec<float> {
+  int16_t base[3];   // floor(X) per axis (periodic axes: modulo n); axes < 2^15 cells
+  int16_t valid;
+  float d[3];        // X - base per axis, in [0, 1)
+  float F[3];
+};
+static_assert(sizeof(NodeRec<float>) == 32, "compact spreading record");
 
 // Per-simulation device descriptor.  Lives in device memory; kernels take an
 // array of these (one entry for a single simulation, many for a batch).

@@ -287,19 +287,21 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         axis_cells(q.base[1], oy, ny, S.wall[1], by, ly, my);
         axis_cells(q.base[2], oz, nz, S.wall[2], bz, lz, mz);
         const R fx = q.F[0] * sc, fy = q.F[1] * sc, fz = q.F[2] * sc;
+        R w3[3][4];
+        rec_weights(q, S.delta, w3);
 #pragma unroll
         for (int dz = 0; dz < 4; ++dz) {
           if (!((mz >> dz) & 1)) continue;
 #pragma unroll
           for (int dy = 0; dy < 4; ++dy) {
             if (!((my >> dy) & 1)) continue;
-            const R wyz = q.w[1][dy] * q.w[2][dz];
+            const R wyz = w3[1][dy] * w3[2][dz];
             const R gx = fx * wyz, gy = fy * wyz, gz = fz * wyz;
             const int row = bx * ly[dy] + kBrickThreads * lz[dz];
 #pragma unroll
             for (int dx = 0; dx < 4; ++dx) {
               if (!((mx >> dx) & 1)) continue;
-              const R wx = q.w[0][dx];
+              const R wx = w3[0][dx];
               const int li = row + lx[dx];
               FA::add(&gq[0][li], FA::fix(gx * wx));
               FA::add(&gq[1][li], FA::fix(gy * wx));

@@ -89,6 +89,7 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   if (!d) return fail(IBL_ERR_ARG, "null descriptor");
   for (int a = 0; a < 3; ++a) {
     if (d->n[a] < 4) return fail(IBL_ERR_ARG, "every axis needs at least 4 cells");
+    if (d->n[a] > 32767) return fail(IBL_ERR_ARG, "at most 32767 cells per axis");
     if (d->wall[a] != 0 && d->wall[a] != 1) return fail(IBL_ERR_ARG, "wall flag must be 0 or 1");
   }
   if (!(d->tau > 0.5)) return fail(IBL_ERR_ARG, "tau must exceed 1/2");
