@@ -29,6 +29,7 @@ struct Store<kF64> {
   using R = double;
   __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { p[i] = hq; }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return p[i]; }
 };
 template <>
@@ -37,6 +38,7 @@ struct Store<kF32> {
   using R = float;
   __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
+  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { p[i] = hq; }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)p[i]; }
 };
 template <>
@@ -49,6 +51,24 @@ struct Store<kF16> {
   }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) {
     ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(hq));
+  }
+  // Stochastic rounding to binary16 for the timestep's stores: a per-step
+  // increment below half a binary16 ulp (a small body force on offsets of
+  // ~1e-3) is lost every step under round-to-nearest; rounding up with
+  // probability equal to the discarded fraction keeps its expected value.
+  // The random bits hash (cell, step, population), so runs stay bitwise
+  // reproducible.
+  // `salt` is a per-(cell, step) hash; each population mixes in its own index.
+  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t salt, int q) {
+    uint32_t r = (salt ^ ((uint32_t)q * 0x9E3779B9u)) * 0x2c1b3c6du;
+    r ^= r >> 13;
+    const uint32_t b = __float_as_uint(hq), a = b & 0x7fffffffu;
+    // binary16 normal range: add 13 random bits below its last mantissa bit,
+    // then drop them (the result is a binary16 value, converted exactly);
+    // subnormal, zero and out-of-range values round to nearest
+    const bool normal = a >= 0x38800000u && a < 0x477fe000u;
+    const uint32_t t = ((a + (r & 0x1fffu)) & ~0x1fffu) | (b & 0x80000000u);
+    ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(normal ? __uint_as_float(t) : hq));
   }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
 };

@@ -221,9 +221,10 @@ struct FixAcc<double> {
   __device__ static void add(A* p, A v) { atomicAdd((unsigned long long*)p, (unsigned long long)v); }
 };
 
-// FP32 / FP16: registers capped for 5 waves per SIMD (measured best; 6 spills)
+// FP32: registers capped for 5 waves per SIMD (measured best; 6 spills); FP16
+// (stochastic rounding) spills under that cap and runs best uncapped
 template <int ST>
-__global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(const SimDev* __restrict__ sims,
+__global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
@@ -332,7 +333,9 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
     if (x < nx && y < ny) {
       const int64_t nc = S.ncell;
-      const int par = (int)(*S.step & 1);
+      const int64_t stepn = *S.step;
+      const int par = (int)(stepn & 1);
+      const uint32_t salt = (uint32_t)stepn * 0x85EBCA77u + 0x165667B1u;
       const GLB T* src = (const GLB T*)S.f[par];
       GLB T* dst = (GLB T*)S.f[par ^ 1];
       GLB R4<R>* uf = (GLB R4<R>*)S.u;
@@ -385,6 +388,11 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
           continue;
         }
         if (S.has_ib) *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
+        // per-(cell, step) random bits for stochastic rounding (FP16 storage)
+        uint32_t csalt = (uint32_t)cell * 0x9E3779B1u + salt;
+        csalt ^= csalt >> 15;
+        csalt *= 0x2c1b3c6du;
+        csalt ^= csalt >> 12;
         // collision, Eq. (1), (2), (4), in offset form h = f - w
         const R usq = ux * ux + uy * uy + uz * uz;
         const R ug = ux * gx + uy * gy + uz * gz;
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
           const R heq = w * (drho + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq));
           const R Fq = pre * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
           // post-collision value, stored in place; the next step pulls it
-          Store<ST>::put(dst, (int64_t)q * nc + cell, q, h[q] - om * (h[q] - heq) + Fq);
+          Store<ST>::put_sr(dst, (int64_t)q * nc + cell, h[q] - om * (h[q] - heq) + Fq, csalt, q);
         }
       }
     }
