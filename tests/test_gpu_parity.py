@@ -70,16 +70,21 @@ def _compare(spec, g, o, storage, tol=None, name=""):
     return eu
 
 
-def test_poiseuille_closed_form_on_gpu():
+@pytest.mark.parametrize("n,gx", [((8, 6, 12), 1e-5), ((8, 8, 64), 1e-6)])
+def test_poiseuille_closed_form_on_gpu(n, gx):
     """Plain lattice (no capsules): the GPU reaches the discrete Poiseuille
-    solution of the BGK + forcing + bounce-back scheme.  This steady state is
-    the hardest case for FP16 offsets: each step's force increment (~6e-7)
-    is a few binary16 ulps of h (~2e-4), so rounding biases the steady state;
-    the band states the measured error (~1e-2)."""
-    n = (8, 6, 12)
-    tau, gx = 0.8, 1e-5
+    solution of the BGK + forcing + bounce-back scheme.  Steady states are the
+    hardest case for reduced storage: the same populations recur every step,
+    so rounding that is biased for them shifts the steady state.  The wider
+    channel at g = 1e-6 puts each step's force increment below half a
+    binary16 ulp of the offsets: round-to-nearest storage stalled there at
+    ~64% of u_max, stochastic rounding keeps the expected increment.
+    Bands: pointwise max-norm error of u (FP16: single stochastic-rounding
+    realisation) and the error of the profile averaged over the periodic
+    directions."""
+    tau = 0.8
     nu = (tau - 0.5) / 3
-    for storage, tol in (("f64", 1e-12), ("f32", 2e-5), ("f16", 2e-2)):
+    for storage, tol, tol_mean in (("f64", 1e-12, 1e-12), ("f32", 4e-4, 4e-4), ("f16", 1e-2, 2e-3)):
         d = ibl.make_desc(n, tau, g_body=(gx, 0, 0), wall=(0, 0, 1), storage=storage)
         s = ibl.Sim(d)
         s.step(int(40 * n[2] ** 2 / nu))
@@ -89,7 +94,11 @@ def test_poiseuille_closed_form_on_gpu():
         L = (tau - 0.5) ** 2
         ana = gx / (2 * nu) * (z - 0.5) * (n[2] - 1.5 - z) + gx / nu * (2 * L / 3 - 1.0 / 8)
         err = np.abs(u[0, 1:-1] - ana[:, None, None]).max() / ana.max()
+        err_mean = np.abs(u[0, 1:-1].mean(axis=(1, 2)) - ana).max() / ana.max()
+        _record("poiseuille-%dx%dx%d" % n, storage=storage, u_max=float(err), u_l2=float(err_mean), rho=0.0,
+                g_max=0.0, g_l2=0.0, x_abs=0.0, x_rel=0.0, F=0.0)
         assert err < tol, (storage, err)
+        assert err_mean < tol_mean, (storage, err_mean)
 
 
 def test_couette_plain_f64_matches_oracle():
