@@ -182,6 +182,104 @@ def run_served(storage, seconds, rate, step_scale, seed=1005):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
 
 
+def tile_spec(spec, reps=(2, 2, 2)):
+    """The cells of `spec` repeated reps[a] times along each axis (every copy
+    keeps its wall clearance, so copies never overlap)."""
+    from paper_1704_04551_amd import workloads as W
+    n = tuple(spec.n[a] * reps[a] for a in range(3))
+    caps = []
+    for kz in range(reps[2]):
+        for ky in range(reps[1]):
+            for kx in range(reps[0]):
+                sh = np.array([kx * spec.n[0], ky * spec.n[1], kz * spec.n[2]], float)
+                for c in spec.capsules:
+                    caps.append(W.Capsule(c.x + sh, c.x_ref + sh, c.tris, c.ks, c.kb, c.shape_key))
+    return W.SimSpec(n=n, tau=spec.tau, g_body=spec.g_body, wall=spec.wall, delta=spec.delta,
+                     capsules=caps, steps=spec.steps, seed=spec.seed,
+                     name="rbc-channel-%dx%dx%d-tiled" % n)
+
+
+def precision_sweep(args):
+    """Config of the precision study: throughput of FP32 vs FP16-offset
+    storage on a 512x256x256 channel; FP32 and FP16 errors against the FP64
+    oracle on a separate 64^3 channel; steady Poiseuille u_max error per
+    storage."""
+    import torch
+    from paper_1704_04551_amd import ibl
+    from paper_1704_04551_amd import workloads as W
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
+    out = {"mode": "precision-sweep"}
+    # (i) throughput, 512 x 256 x 256 (the seeded 256 x 128 x 128 layout tiled 2 x 2 x 2)
+    big = tile_spec(load_spec(args))
+    _log("sweep: %s, %d cells, %d nodes" % (big.name, len(big.capsules), big.nodes))
+    thr = {}
+    for st in ("f32", "f16"):
+        sim = ibl.Sim.from_spec(big, storage=st)
+        sim.step(10)
+        sim.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(args.sweep_steps)
+        sim.sync()
+        dt = time.perf_counter() - t0
+        thr[st] = {"mlups": round(big.cells * args.sweep_steps / dt / 1e6, 1),
+                   "ms_per_step": round(dt * 1e3 / args.sweep_steps, 4), "health": sim.conservation()[2]}
+        _log("sweep: %s %s" % (st, thr[st]))
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["throughput_512x256x256"] = {"workload": big.name, "cells": big.cells, "capsules": len(big.capsules),
+                                     "nodes": big.nodes, "steps": args.sweep_steps, **thr}
+    # (ii) 64^3 channel of the same physics vs the FP64 oracle
+    crop = W.config_rbc_channel(n=(64, 64, 64), count=200, seed=1003)
+    k = args.sweep_crop_steps
+    _log("sweep: crop %d cells, %d nodes, %d steps" % (len(crop.capsules), crop.nodes, k))
+    o = oracle_from_spec(crop)
+    t0 = time.perf_counter()
+    for i in range(0, k, 100):
+        o.step(min(100, k - i))
+        _log("sweep: oracle step %d" % min(k, i + 100))
+    tor = time.perf_counter() - t0
+    _, uo, _ = o.observe()
+    mask = fluid_mask(crop)
+    errs = {}
+    for st in ("f64", "f32", "f16"):
+        g = ibl.Sim.from_spec(crop, storage=st)
+        g.step(k)
+        g.sync()
+        _, ug, _ = g.fields(rho=False, g=False)
+        umax, ul2 = field_err(ug, uo, mask)
+        xa = xr = 0.0
+        for m, c in enumerate(crop.capsules):
+            a, r = node_err(g.nodes(m)[0], o.nodes(m)[0], c.x)
+            xa, xr = max(xa, a), max(xr, r)
+        errs[st] = {"u_max_rel": umax, "u_l2_rel": ul2, "x_max_abs_lu": xa, "x_max_rel_to_displacement": xr}
+        _log("sweep: crop %s %s" % (st, errs[st]))
+        g.close()
+    out["crop_64_vs_fp64_oracle"] = {"cells": crop.cells, "capsules": len(crop.capsules), "nodes": crop.nodes,
+                                     "steps": k, "oracle_s": round(tor, 1), **errs}
+    # (iii) plane Poiseuille 64 x 64 x 256 (walls on x, flow along z) at steady state
+    pz = W.config_poiseuille()
+    nu = (pz.tau - 0.5) / 3.0
+    lam = (pz.tau - 0.5) ** 2
+    nw = pz.n[0]
+    zc = np.arange(nw, dtype=float)
+    exact = pz.g_body[2] / (2 * nu) * (zc - 0.5) * (nw - 1.5 - zc) + pz.g_body[2] / nu * (2 * lam / 3 - 0.125)
+    umax_exact = exact[1:-1].max()
+    pois = {}
+    for st in ("f64", "f32", "f16"):
+        g = ibl.Sim.from_spec(pz, storage=st)
+        g.step(args.sweep_poiseuille_steps)
+        g.sync()
+        _, ug, _ = g.fields(rho=False, g=False)
+        pois[st] = {"u_max": float(ug[2].max()), "u_max_rel_err": float(abs(ug[2].max() - umax_exact) / umax_exact)}
+        _log("sweep: poiseuille %s %s" % (st, pois[st]))
+        g.close()
+    out["poiseuille_64x64x256"] = {"steps": args.sweep_poiseuille_steps, "u_max_exact": umax_exact, **pois}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +295,11 @@ def main():
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
     ap.add_argument("--cache", default=os.path.join(tempfile.gettempdir(), "ibl_rbc_channel_spec.npz"),
                     help="cache of the generated RBC node arrays ('' disables)")
+    ap.add_argument("--precision-sweep", action="store_true",
+                    help="only run the precision study (its own JSON line; several minutes)")
+    ap.add_argument("--sweep-steps", type=int, default=100)
+    ap.add_argument("--sweep-crop-steps", type=int, default=1000)
+    ap.add_argument("--sweep-poiseuille-steps", type=int, default=150000)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -210,6 +313,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        return
+    if args.precision_sweep:
+        precision_sweep(args)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
