@@ -270,10 +270,6 @@ __device__ __forceinline__ void rec_weights(const NodeRec<float>& q, int kind, f
   for (int a = 0; a < 3; ++a) delta_weights_r<float>(kind, q.d[a], w[a]);
 }
 
-template <typename R>
-struct alignas(4 * sizeof(R)) R4 {
-  R x, y, z, w;
-};
 
 __device__ __forceinline__ bool solid_cell(const SimDev& S, int x, int y, int z) {
   return (S.wall[0] && (x == 0 || x == S.n[0] - 1)) || (S.wall[1] && (y == 0 || y == S.n[1] - 1)) ||

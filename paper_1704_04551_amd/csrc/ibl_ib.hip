@@ -500,7 +500,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       node = list[tid];
       q = *(const NodeRec<R>*)(rec + node);
     }
-    const GLB R4<R>* u4 = (const GLB R4<R>*)S.u;
+    const GLB R* uf = (const GLB R*)S.u;  // [3][ncell]
+    const int64_t ncl = S.ncell;
     for (int t = tid; t < kCubeTile; t += blockDim.x) {
       const int tz = t / exy, rr = t - tz * exy, ty = rr / ex, tx = rr - ty * ex;
       const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
@@ -509,10 +510,10 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
       R vx = (R)0, vy = (R)0, vz = (R)0;
       if (in) {
-        const R4<R> v = *(const R4<R>*)(u4 + (cx + (int64_t)n0 * (cy + (int64_t)n1 * cz)));
-        vx = v.x;
-        vy = v.y;
-        vz = v.z;
+        const int64_t c = cx + (int64_t)n0 * (cy + (int64_t)n1 * cz);
+        vx = uf[c];
+        vy = uf[ncl + c];
+        vz = uf[2 * ncl + c];
       }
       ut[0][t] = vx;
       ut[1][t] = vy;

@@ -109,7 +109,7 @@ struct SimDev {
   int32_t maxn;           // SoA stride of the node arrays (capacity)
   // state
   IBL_G(void) f[2];             // populations, [19][ncell] in storage format
-  IBL_G(void) u;                // [ncell] velocity as 4-vectors (compute precision)
+  IBL_G(void) u;                // [3][ncell] velocity (compute precision)
   IBL_G(void) g;                // [3][ncell] spread force (compute precision; observation only)
   IBL_G(void) rho;              // [ncell] density (observation only)
   IBL_G(double) X;              // [3][max_nodes] positions

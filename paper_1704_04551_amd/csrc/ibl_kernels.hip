@@ -80,7 +80,7 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
   using R = RealOf<ST>;
   const int64_t cell = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
   const int c[3] = {x, y, z};
-  GLB R4<R>* u = (GLB R4<R>*)S.u;
+  GLB R* u = (GLB R*)S.u;  // [3][ncell]
   GLB R* g = (GLB R*)S.g;
   GLB R* rho = (GLB R*)S.rho;
   for (int a = 0; a < 3; ++a) g[a * S.ncell + cell] = (R)0;
@@ -94,7 +94,9 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
   double u0[3] = {0.0, 0.0, 0.0};
   if (sa >= 0) {
     const double* v = (c[sa] == 0) ? S.ulo[sa] : S.uhi[sa];
-    *(R4<R>*)(u + cell) = R4<R>{(R)v[0], (R)v[1], (R)v[2], (R)0};
+    u[cell] = (R)v[0];
+    u[S.ncell + cell] = (R)v[1];
+    u[2 * S.ncell + cell] = (R)v[2];
 #pragma unroll
     for (int q = 0; q < kQ; ++q) {
       Store<ST>::put(f0, (int64_t)q * S.ncell + cell, q, (R)0);
@@ -122,7 +124,9 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
     return wq(q) * (3.0 * cu + 4.5 * cu * cu - 1.5 * vv);
   };
   u_init(c, u0);
-  *(R4<R>*)(u + cell) = R4<R>{(R)u0[0], (R)u0[1], (R)u0[2], (R)0};
+  u[cell] = (R)u0[0];
+  u[S.ncell + cell] = (R)u0[1];
+  u[2 * S.ncell + cell] = (R)u0[2];
   // stored populations are post-collision values that the first step's
   // pull turns into f_eq(1, u0): the one read by the consumer x + c_q, or,
   // where x + c_q is a wall layer, the bounce-back source of x itself
@@ -338,7 +342,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
       const uint32_t salt = (uint32_t)stepn * 0x85EBCA77u + 0x165667B1u;
       const GLB T* src = (const GLB T*)S.f[par];
       GLB T* dst = (GLB T*)S.f[par ^ 1];
-      GLB R4<R>* uf = (GLB R4<R>*)S.u;
+      GLB R* uf = (GLB R*)S.u;  // [3][ncell]
       const R om = (R)(1.0 / S.tau);
       const R pre = (R)(1.0 - 0.5 / S.tau);
 #pragma unroll 1
@@ -380,14 +384,20 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
         const R uz = (jz + (R)0.5 * gz) * irho;
         if (mode == 1) {
           ((GLB R*)S.rho)[cell] = rho;
-          *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
+          uf[cell] = ux;
+          uf[nc + cell] = uy;
+          uf[2 * nc + cell] = uz;
           GLB R* gf = (GLB R*)S.g;
           gf[cell] = gix;
           gf[nc + cell] = giy;
           gf[2 * nc + cell] = giz;
           continue;
         }
-        if (S.has_ib) *(R4<R>*)(uf + cell) = R4<R>{ux, uy, uz, (R)0};
+        if (S.has_ib) {
+          uf[cell] = ux;
+          uf[nc + cell] = uy;
+          uf[2 * nc + cell] = uz;
+        }
         // per-(cell, step) random bits for stochastic rounding (FP16 storage)
         uint32_t csalt = (uint32_t)cell * 0x9E3779B1u + salt;
         csalt ^= csalt >> 15;

@@ -135,7 +135,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   };
   L.f0 = take((size_t)kQ * ncell * storage_bytes(st));
   L.f1 = take((size_t)kQ * ncell * storage_bytes(st));
-  L.u = take((size_t)4 * ncell * real_bytes(st));
+  L.u = take((size_t)3 * ncell * real_bytes(st));
   L.g = take((size_t)3 * ncell * real_bytes(st));
   L.rho = take((size_t)ncell * real_bytes(st));
   L.X = take(3 * maxn * 8);
@@ -643,12 +643,10 @@ ibl_status ibl_read_fields(ibl_sim S, double* rho, double* u, double* g) {
       if (solid(c)) rho[c] = 0.0;
   }
   if (u) {
-    std::vector<char> raw4((size_t)4 * nc * rb);
-    std::vector<double> tmp((size_t)4 * nc);
-    HIPCHK(hipMemcpy(raw4.data(), d.u, (size_t)4 * nc * rb, hipMemcpyDeviceToHost));
-    if (dbl) fields_to_host<double>(raw4, 4 * nc, tmp.data()); else fields_to_host<float>(raw4, 4 * nc, tmp.data());
+    HIPCHK(hipMemcpy(raw.data(), d.u, (size_t)3 * nc * rb, hipMemcpyDeviceToHost));
+    if (dbl) fields_to_host<double>(raw, 3 * nc, u); else fields_to_host<float>(raw, 3 * nc, u);
     for (int64_t c = 0; c < nc; ++c)
-      for (int a = 0; a < 3; ++a) u[a * nc + c] = solid(c) ? 0.0 : tmp[4 * c + a];
+      if (solid(c)) u[c] = u[nc + c] = u[2 * nc + c] = 0.0;
   }
   if (g) {
     HIPCHK(hipMemcpy(raw.data(), d.g, (size_t)3 * nc * rb, hipMemcpyDeviceToHost));
