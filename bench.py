@@ -24,6 +24,8 @@ Prints one JSON line.
   the same simulations run one after another.
 * ``served``: a Poisson stream of Jeffery-orbit jobs through the serving loop
   (continuous batching): p50/p99 latency and aggregate MLUPS.
+* ``autotune``: the lattice brick width is timed for 16 / 32 / 64 cells on the
+  workload first (``--no-autotune`` or ``--brick-x`` to skip).
 """
 from __future__ import annotations
 
@@ -43,10 +45,10 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def lattice_traffic(storage):
+def lattice_traffic(storage, brick_x):
     """Counter-measured HBM bytes of one collide-stream launch, from the
-    committed profiler summary of this workload, if the kernel sources are
-    still the ones it was measured on (else None)."""
+    committed profiler summary of this workload, if the kernel sources and the
+    brick width are still the ones it was measured with (else None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_lattice_rbc_channel_256x128x128_%s_traffic.md" % storage)
@@ -55,7 +57,8 @@ def lattice_traffic(storage):
     text = open(path).read()
     m_b = re.search(r"^traffic_bytes_k_lattice: (\d+)$", text, re.M)
     m_h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
-    if not (m_b and m_h):
+    m_w = re.search(r"^brick_x: (\d+)$", text, re.M)
+    if not (m_b and m_h and m_w) or int(m_w.group(1)) != brick_x:
         return None
     csrc = os.path.join(ROOT, "paper_1704_04551_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read()
@@ -289,6 +292,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="use the built-in brick width")
+    ap.add_argument("--brick-x", type=int, default=0, choices=[0, 16, 32, 64],
+                    help="fixed brick width (skips the autotuner)")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the served run")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -328,8 +334,16 @@ def main():
 
     _log("generating workload")
     spec = load_spec(args)
+    tuned = None
+    brick_x = args.brick_x
+    if not brick_x and not args.no_autotune:
+        from paper_1704_04551_amd.autotune import tune_brick_x
+        _log("autotuning the brick width")
+        brick_x, timings = tune_brick_x(spec, args.storage, steps=30, warmup=5, use_memo=False)
+        tuned = {"brick_x": brick_x, "ms_per_step": {str(k): round(v, 4) for k, v in timings.items()}}
+        _log("autotune: %s" % tuned)
     _log("%d cells, %d nodes; creating simulation" % (len(spec.capsules), spec.nodes))
-    sim = ibl.Sim.from_spec(spec, storage=args.storage, device="cuda:0")
+    sim = ibl.Sim.from_spec(spec, storage=args.storage, device="cuda:0", brick_x=brick_x)
     sim.step(args.warmup)
     sim.sync()
     _log("warmup done")
@@ -375,10 +389,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_lattice (collide-stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": lattice_traffic(args.storage),
+                     "traffic": lattice_traffic(args.storage, brick_x or 64),
                      "bytes_per_launch": lat_bytes, "launch_ms": round(lat_ms, 5)},
         "step_roofline_frac": round(cells * 2 * 19 * sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {k: round(v, 5) for k, v in phases.items()},
+        "brick_x": brick_x or None,
+        "autotune": tuned,
         "health": health,
     }
     sim.close()

@@ -94,6 +94,11 @@ typedef struct {
   int32_t max_templates;   /* capacity: distinct mesh templates */
   int32_t max_template_nodes; /* capacity: nodes summed over templates */
   int32_t max_template_edges; /* capacity: edges summed over templates */
+  int32_t brick_x;         /* lattice brick width along x: 16, 32 or 64 cells (bricks are
+                              brick_x x 256/brick_x x 4 cells, one workgroup each), or 0
+                              for the widest that the x extent fills.  A tuning knob:
+                              results agree to the spreading's fixed-point resolution,
+                              not bitwise, across widths. */
 } ibl_sim_desc;
 
 typedef struct ibl_sim_s* ibl_sim;
@@ -109,7 +114,8 @@ ibl_status ibl_sim_bytes(const ibl_sim_desc* desc, size_t* out_bytes);
  * populations to equilibrium at rho = 1 and the initial velocity (Sec. 2.1).
  * hip_stream: the hipStream_t to run on, or NULL for a stream the library
  * creates (non-blocking, default priority) and destroys.
- * Errors: IBL_ERR_ARG (tau <= 1/2, n < 4, bad enums), IBL_ERR_NOMEM (arena too
+ * Errors: IBL_ERR_ARG (tau <= 1/2, n < 4 or > 32767, bad enums, brick_x not
+ * 0/16/32/64, 2 x cells x element bytes >= 4 GiB), IBL_ERR_NOMEM (arena too
  * small), IBL_ERR_DEVICE. */
 ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t arena_bytes,
                           void* hip_stream, ibl_sim* out);

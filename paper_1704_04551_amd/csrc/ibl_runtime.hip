@@ -43,15 +43,12 @@ constexpr int kGraphSteps = 16;
 // Force-kernel variant (tuning knob; IBL_FORCES=split selects the edge / node
 // split for every template, the default is one LDS workgroup per capsule).
 // Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x kBrickZ cells,
-// bs[0] the widest of 64, 32, 16 that the x extent fills (long x rows keep
-// the streaming accesses in whole cache lines).  IBL_BRICK_X=16|32|64
-// overrides the choice (tuning).
+// bs[0] the descriptor's brick_x, or by default the widest of 64, 32, 16 that
+// the x extent fills (long x rows keep the streaming accesses in whole cache
+// lines).
 void brick_shape(const ibl_sim_desc* d, int bs[3]) {
   int bx = d->n[0] >= 64 ? 64 : (d->n[0] >= 32 ? 32 : 16);
-  if (const char* v = getenv("IBL_BRICK_X")) {
-    const int t = atoi(v);
-    if (t == 16 || t == 32 || t == 64) bx = t;
-  }
+  if (d->brick_x) bx = d->brick_x;
   bs[0] = bx;
   bs[1] = kBrickThreads / bx;
   bs[2] = kBrickZ;
@@ -94,6 +91,8 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   }
   if (!(d->tau > 0.5)) return fail(IBL_ERR_ARG, "tau must exceed 1/2");
   if (d->storage < 0 || d->storage > 2) return fail(IBL_ERR_ARG, "unknown storage");
+  if (d->brick_x != 0 && d->brick_x != 16 && d->brick_x != 32 && d->brick_x != 64)
+    return fail(IBL_ERR_ARG, "brick_x must be 0, 16, 32 or 64");
   if (d->delta < 0 || d->delta > 1) return fail(IBL_ERR_ARG, "unknown delta kernel");
   if (d->init_profile < 0 || d->init_profile > 1) return fail(IBL_ERR_ARG, "unknown init profile");
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||

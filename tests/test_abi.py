@@ -40,6 +40,16 @@ def _desc(**kw):
     return ibl.make_desc(**base)
 
 
+def test_brick_width_changes_layout_not_validity():
+    """Every allowed brick width is a valid description; narrower bricks mean
+    more candidate lists (the arena grows)."""
+    kw = dict(n=(64, 36, 20), max_nodes=1000, max_meshes=1, max_templates=1, max_template_nodes=1000,
+              max_template_edges=3000)
+    sizes = [ibl.sim_bytes(_desc(brick_x=bx, **kw)) for bx in (64, 32, 16)]
+    assert sizes[0] == ibl.sim_bytes(_desc(brick_x=0, **kw))  # 64 is the default for nx = 64
+    assert sizes[0] <= sizes[1] <= sizes[2]
+
+
 def test_sim_bytes_scales_with_storage():
     b64 = ibl.sim_bytes(_desc(storage="f64"))
     b32 = ibl.sim_bytes(_desc(storage="f32"))
@@ -52,7 +62,9 @@ def test_sim_bytes_scales_with_storage():
 
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(n=(3, 32, 32)), dict(storage=7),
-                                dict(delta=5), dict(init_profile=3), dict(max_nodes=-1)])
+                                dict(delta=5), dict(init_profile=3), dict(max_nodes=-1),
+                                dict(brick_x=8), dict(brick_x=128), dict(n=(32768, 4, 4)),
+                                dict(n=(1024, 1024, 1024), storage="f32")])
 def test_invalid_descriptor_rejected(kw):
     with pytest.raises(ibl.IBLError) as e:
         ibl.sim_bytes(_desc(**kw))
