@@ -207,24 +207,26 @@ __device__ __forceinline__ void delta_weights(int kind, double d, double w[4]) {
 __device__ __forceinline__ void edge_forces(D3 v0, D3 v1, D3 v2, D3 v3, double l0, double c0,
                                             double s0, double ks, double kb, D3& G0, D3& G3,
                                             D3& F1) {
+  // three reciprocals and two square roots per edge (FP64 division is a long
+  // instruction sequence); the rest are products
   const D3 e = sub(v2, v1);
-  const double e2 = dot(e, e), le = sqrt(e2);
-  F1 = scale(e, ks * (le - l0) / le);  // spring pulls v1 toward v2 when stretched
+  const double e2 = dot(e, e), le = sqrt(e2), rle = 1.0 / le, re2 = rle * rle;
+  F1 = scale(e, ks * (le - l0) * rle);  // spring pulls v1 toward v2 when stretched
   G0 = {0.0, 0.0, 0.0};
   G3 = {0.0, 0.0, 0.0};
   if (kb != 0.0) {
     const D3 a = sub(v0, v1);
     const D3 nA = cross(e, a);
     const D3 nB = cross(sub(v3, v2), e);
-    const double nA2 = dot(nA, nA), nB2 = dot(nB, nB);
-    const double inv = 1.0 / sqrt(nA2 * nB2);
+    const double rA = 1.0 / dot(nA, nA), rB = 1.0 / dot(nB, nB);
+    const double inv = sqrt(rA * rB);  // 1 / (|nA| |nB|)
     const double ct = dot(nA, nB) * inv;
-    const double st = dot(cross(nA, nB), e) * inv / le;
+    const double st = dot(cross(nA, nB), e) * inv * rle;
     const double dEdth = kb * (st * c0 - ct * s0);  // kb sin(theta - theta0)
-    G0 = scale(nA, dEdth * le / nA2);
-    G3 = scale(nB, dEdth * le / nB2);
-    const double t0 = dot(a, e) / e2;
-    const double t3 = dot(sub(v3, v1), e) / e2;
+    G0 = scale(nA, dEdth * le * rA);
+    G3 = scale(nB, dEdth * le * rB);
+    const double t0 = dot(a, e) * re2;
+    const double t3 = dot(sub(v3, v1), e) * re2;
     F1.x += (t0 - 1.0) * G0.x + (t3 - 1.0) * G3.x;
     F1.y += (t0 - 1.0) * G0.y + (t3 - 1.0) * G3.y;
     F1.z += (t0 - 1.0) * G0.z + (t3 - 1.0) * G3.z;
