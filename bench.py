@@ -23,7 +23,8 @@ Prints one JSON line.
 * ``batched``: 64 uneven simulations in one batched launch sequence against
   the same simulations run one after another.
 * ``served``: a Poisson stream of Jeffery-orbit jobs through the serving loop
-  (continuous batching): p50/p99 latency and aggregate MLUPS.
+  (continuous batching) and, on the same stream, one job at a time (the
+  plain form): p50/p99 latency and aggregate MLUPS of each.
 * ``autotune``: the lattice brick width is timed for 16 / 32 / 64 cells on the
   workload first (``--no-autotune`` or ``--brick-x`` to skip).
 """
@@ -170,19 +171,27 @@ def run_served(storage, seconds, rate, step_scale, seed=1005):
     `step_scale`, so the stream fits the window."""
     import torch
     from paper_1704_04551_amd import workloads as W
-    from paper_1704_04551_amd.serve import GpuBackend, Server, poisson_jobs
+    from paper_1704_04551_amd.serve import GpuBackend, Job, Server, poisson_jobs
     lo, hi = max(1, int(2000 * step_scale)), max(1, int(20000 * step_scale))
     jobs = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, steps=(lo, hi)), seed)
     free, total = torch.cuda.mem_get_info()
     pool = int(0.5 * free)
-    srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=64, queue_cap=4096)
-    try:
-        st = srv.run(jobs, time_limit=3 * seconds)
-    finally:
-        srv.close()
-    st.update({"rate_jobs_s": rate, "window_s": seconds, "jobs": len(jobs),
-               "job_steps": [lo, hi], "pool_bytes": pool})
-    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    out = {}
+    # continuous batching, then the plain form (one job at a time, first come
+    # first served) on the same arrival stream
+    for name, slots in (("batched", 64), ("plain", 1)):
+        stream = [Job(j.jid, j.spec, j.arrival, j.steps) for j in jobs]
+        srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=slots, queue_cap=4096)
+        try:
+            st = srv.run(stream, time_limit=3 * seconds)
+        finally:
+            srv.close()
+        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+        _log("served (%s): %s" % (name, out[name]))
+    out.update({"rate_jobs_s": rate, "window_s": seconds, "jobs": len(jobs), "job_steps": [lo, hi],
+                "pool_bytes": pool, "p50_s": out["batched"]["p50_s"], "p99_s": out["batched"]["p99_s"],
+                "mlups": out["batched"]["mlups"]})
+    return out
 
 
 def tile_spec(spec, reps=(2, 2, 2)):
@@ -296,7 +305,7 @@ def main():
     ap.add_argument("--brick-x", type=int, default=0, choices=[0, 16, 32, 64],
                     help="fixed brick width (skips the autotuner)")
     ap.add_argument("--batched-steps", type=int, default=500)
-    ap.add_argument("--serve-seconds", type=float, default=20.0, help="0 skips the served run")
+    ap.add_argument("--serve-seconds", type=float, default=15.0, help="0 skips the served runs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
     ap.add_argument("--cache", default=os.path.join(tempfile.gettempdir(), "ibl_rbc_channel_spec.npz"),

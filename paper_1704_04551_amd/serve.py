@@ -222,9 +222,9 @@ class Server:
             self.chunks += 1
             self._retire(t0)
         wall = self.clock() - t0
-        return self.stats(wall)
+        return self.stats(wall, not_arrived=len(pending))
 
-    def stats(self, wall: float) -> dict:
+    def stats(self, wall: float, not_arrived: int = 0) -> dict:
         lat = sorted(j.latency for j in self.finished)
         def pct(p):
             if not lat:
@@ -234,7 +234,7 @@ class Server:
             "wall_s": wall,
             "finished": len(self.finished),
             "rejected": len(self.rejected),
-            "unfinished": len(self.queue) + len(self.resident),
+            "unfinished": len(self.queue) + len(self.resident) + not_arrived,
             "p50_s": pct(50),
             "p99_s": pct(99),
             "mlups": self.cell_steps / wall / 1e6 if wall > 0 else 0.0,
