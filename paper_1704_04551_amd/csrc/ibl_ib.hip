@@ -73,13 +73,18 @@ __device__ __forceinline__ void write_record(const SimDev& S, int gid, const int
 
 // Spreading record and validity check of one node; fills the bricks its
 // stencil touches.
+// The node arrays F and U are outputs of observation only (mode 1): a step
+// (mode 0) passes forces to spreading through the records and velocities to
+// the node update in registers.
 template <typename R>
 __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3],
-                            NodeBricks& nb) {
+                            NodeBricks& nb, int mode) {
   const int64_t ms = (int64_t)S.maxn;
-  S.F[gid] = Fv[0];
-  S.F[ms + gid] = Fv[1];
-  S.F[2 * ms + gid] = Fv[2];
+  if (mode == 1) {
+    S.F[gid] = Fv[0];
+    S.F[ms + gid] = Fv[1];
+    S.F[2 * ms + gid] = Fv[2];
+  }
   int valid = 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -107,9 +112,11 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
   nb.base[1] = base[1];
   nb.base[2] = base[2];
   if (!valid) {  // on no candidate list: interpolation never visits it
-    S.U[gid] = 0.0;
-    S.U[ms + gid] = 0.0;
-    S.U[2 * ms + gid] = 0.0;
+    if (mode == 1) {
+      S.U[gid] = 0.0;
+      S.U[ms + gid] = 0.0;
+      S.U[2 * ms + gid] = 0.0;
+    }
     return;
   }
   int p0[3], p1[3], h1[3];
@@ -212,11 +219,11 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, const NodeBric
 // Record + aggregated append of one node per thread (active = false: no node).
 template <typename R>
 __device__ void emit_nodes(const SimDev& S, BinTable& T, bool active, int gid, const double Xp[3],
-                           const double Fv[3]) {
+                           const double Fv[3], int mode) {
   NodeBricks nb;
   nb.mask = 0;
   nb.rare = 0;
-  if (active) make_record<R>(S, gid, Xp, Fv, nb);
+  if (active) make_record<R>(S, gid, Xp, Fv, nb, mode);
   // largest force component in the precision the spreading reads (float)
   const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
   const uint32_t fbits = __float_as_uint(isfinite(fm) ? fm : 0.f);
@@ -324,8 +331,8 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
     gather_node<R>(S, pe, actb ? S.inc_ptr[row0 + ib] : 0, actb ? S.inc_ptr[row0 + ib + 1] : 0, e0, Fb);
     const double Xa[3] = {acta ? X0[ia] : 0.0, acta ? X0[ms + ia] : 0.0, acta ? X0[2 * ms + ia] : 0.0};
     const double Xb[3] = {actb ? X0[ib] : 0.0, actb ? X0[ms + ib] : 0.0, actb ? X0[2 * ms + ib] : 0.0};
-    emit_nodes<R>(S, bt, acta, off + ia, Xa, Fa);
-    if (nn > NT) emit_nodes<R>(S, bt, actb, off + ib, Xb, Fb);  // uniform
+    emit_nodes<R>(S, bt, acta, off + ia, Xa, Fa, mode);
+    if (nn > NT) emit_nodes<R>(S, bt, actb, off + ib, Xb, Fb, mode);  // uniform
     __syncthreads();  // shares of this capsule read before the next one's are written
   }
 }
@@ -412,7 +419,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
       }
       const int gid = off + i;
       const double Xp[3] = {act ? S.X[gid] : 0.0, act ? S.X[ms + gid] : 0.0, act ? S.X[2 * ms + gid] : 0.0};
-      emit_nodes<R>(S, bt, act, gid, Xp, F);
+      emit_nodes<R>(S, bt, act, gid, Xp, F, mode);
     }
   }
 }
@@ -460,15 +467,17 @@ __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCube
     }
   const int64_t ms = (int64_t)S.maxn;
   const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
-  S.U[node] = ux;
-  S.U[ms + node] = uy;
-  S.U[2 * ms + node] = uz;
   if (mode == 0) {
     S.X[node] += ux;
     S.X[ms + node] += uy;
     S.X[2 * ms + node] += uz;
+  } else {
+    S.U[node] = ux;
+    S.U[ms + node] = uy;
+    S.U[2 * ms + node] = uz;
   }
 }
+
 
 template <typename R>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restrict__ sims, Items it,
@@ -501,26 +510,44 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
       q = *(const NodeRec<R>*)(rec + node);
     }
     const GLB R* uf = (const GLB R*)S.u;  // [3][ncell]
-    const int64_t ncl = S.ncell;
-    for (int t = tid; t < kCubeTile; t += blockDim.x) {
-      const int tz = t / exy, rr = t - tz * exy, ty = rr / ex, tx = rr - ty * ex;
-      const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
-      const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
-      const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
-      const bool in = cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
-      R vx = (R)0, vy = (R)0, vz = (R)0;
-      if (in) {
-        const int64_t c = cx + (int64_t)n0 * (cy + (int64_t)n1 * cz);
-        vx = uf[c];
-        vy = uf[ncl + c];
-        vz = uf[2 * ncl + c];
+    const uint32_t ncl = (uint32_t)S.ncell;
+    // the tile's loads are issued in batches of kBatch per lane before their
+    // LDS stores (cell indices fit 32 bits: 2 * cells * element bytes < 4 GiB)
+    constexpr int kIter = (kCubeTile + kInterpThreads - 1) / kInterpThreads;
+    constexpr int kBatch = 9;
+    static_assert(kIter % kBatch == 0, "tile loads in whole batches");
+#pragma unroll 1
+    for (int k0 = 0; k0 < kIter; k0 += kBatch) {
+      R v[kBatch][3];
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int t = tid + (k0 + k) * kInterpThreads;
+        const int tz = t / exy, rr = t - tz * exy, ty = rr / ex, tx = rr - ty * ex;
+        const int cx = w0 ? ox - 1 + tx : margin_wrap(ox - 1 + tx, n0);
+        const int cy = w1 ? oy - 1 + ty : margin_wrap(oy - 1 + ty, n1);
+        const int cz = w2 ? oz - 1 + tz : margin_wrap(oz - 1 + tz, n2);
+        const bool in = t < kCubeTile && cx >= 0 && cx < n0 && cy >= 0 && cy < n1 && cz >= 0 && cz < n2;
+        v[k][0] = v[k][1] = v[k][2] = (R)0;
+        if (in) {
+          const uint32_t c = (uint32_t)(cx + n0 * (cy + n1 * cz));
+          v[k][0] = uf[c];
+          v[k][1] = uf[ncl + c];
+          v[k][2] = uf[2 * ncl + c];
+        }
       }
-      ut[0][t] = vx;
-      ut[1][t] = vy;
-      ut[2][t] = vz;
+#pragma unroll
+      for (int k = 0; k < kBatch; ++k) {
+        const int t = tid + (k0 + k) * kInterpThreads;
+        if (t < kCubeTile) {
+          ut[0][t] = v[k][0];
+          ut[1][t] = v[k][1];
+          ut[2][t] = v[k][2];
+        }
+      }
     }
     __syncthreads();
-    for (int i0 = 0; i0 < cnt; i0 += blockDim.x) {
+#pragma unroll 1
+    for (int i0 = 0; i0 < cnt; i0 += kInterpThreads) {
       if (i0 > 0) {
         node = -1;
         if (i0 + tid < cnt) {
