@@ -299,7 +299,7 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
     const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     const int m = item - it.mesh_off[s];
     const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ 
     const int mi = item / kEdgeChunks, c = item % kEdgeChunks;
     const int s = find_sim(it.mesh_off, it.nsim, mi);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;
+    if (mode == 0 && *S.remaining <= it.sub) continue;
     const int m = mi - it.mesh_off[s];
     const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
     const int mi = item / kNodeChunks, c = item % kNodeChunks;
     const int s = find_sim(it.mesh_off, it.nsim, mi);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     const int m = mi - it.mesh_off[s];
     const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
@@ -488,7 +488,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
   for (int item = xcd_block(); item < it.cube_total; item += gridDim.x) {
     const int s = find_sim(it.cube_off, it.nsim, item);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     const int64_t h = item - it.cube_off[s];
     int cnt = S.hcount[h];
     if (cnt == 0) continue;  // no node has its base here (uniform)

@@ -159,6 +159,10 @@ struct Items {
   const int32_t* red_off;
   const int32_t* mesh_off;
   const int32_t* cube_off;
+  // Index of this timestep within a launch sequence of several: a simulation
+  // takes part while its remaining count exceeds it, at parity (step + sub) & 1.
+  // The counters advance once, after the sequence.
+  int32_t sub;
 };
 
 // Phases of one timestep, in launch order.
@@ -166,7 +170,7 @@ enum Phase : int {
   kPhaseForces = 0,   // membrane forces, spreading records, candidate lists
   kPhaseLattice = 1,  // per brick: force spreading, moments, collision, streaming (u^n written)
   kPhaseInterp = 2,   // velocity interpolation and node update
-  kPhaseAdvance = 3,  // step counter
+  kPhaseAdvance = 3,  // step counter (one step; sequences advance once at their end)
   kNumPhases = 4
 };
 
@@ -181,7 +185,9 @@ hipError_t launch_template_rest(const SimDev* sim, int tmpl, int nedges, const d
                                 hipStream_t s);
 hipError_t launch_phase(int storage, const SimDev* sims, const Items& it, int phase, int mode,
                         hipStream_t s);
-hipError_t launch_step(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s);
+// `steps` timesteps (mode 0) followed by one counter advance, or one
+// observation (mode 1, steps = 1, no advance).
+hipError_t launch_steps(int storage, const SimDev* sims, const Items& it, int steps, int mode, hipStream_t s);
 hipError_t launch_reduce(int storage, const SimDev* sims, const Items& it, hipStream_t s);
 
 }  // namespace ibl

@@ -244,7 +244,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
   for (int item = xcd_block(); item < it.lat_total; item += gridDim.x) {
     const int s = find_sim(it.lat_off, it.nsim, item);
     const SimDev& S = sims[s];
-    if (mode == 0 && *S.remaining <= 0) continue;  // uniform over the workgroup
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     const int64_t b = item - it.lat_off[s];
     int ox, oy, oz;
     brick_origin(S, b, ox, oy, oz);
@@ -337,7 +337,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
     if (x < nx && y < ny) {
       const int64_t nc = S.ncell;
-      const int64_t stepn = *S.step;
+      const int64_t stepn = *S.step + it.sub;
       const int par = (int)(stepn & 1);
       const uint32_t salt = (uint32_t)stepn * 0x85EBCA77u + 0x165667B1u;
       const GLB T* src = (const GLB T*)S.f[par];
@@ -424,13 +424,15 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
 }
 
 // -------------------------------------------------------------- advance --
-__global__ void k_advance(const SimDev* __restrict__ sims, int nsim) {
+// after a sequence of `steps` timesteps: each simulation ran min(remaining, steps)
+__global__ void k_advance(const SimDev* __restrict__ sims, int nsim, int steps) {
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nsim) return;
   const SimDev& S = sims[s];
-  if (*S.remaining > 0) {
-    *S.step += 1;
-    *S.remaining -= 1;
+  const int64_t r = *S.remaining, k = r < steps ? r : (int64_t)steps;
+  if (k > 0) {
+    *S.step += k;
+    *S.remaining = r - k;
   }
 }
 
@@ -547,7 +549,7 @@ static void phase_impl(const SimDev* sims, const Items& it, int phase, int mode,
       launch_interp(ST, sims, it, mode, s);
       break;
     case kPhaseAdvance:
-      if (mode == 0) hipLaunchKernelGGL(k_advance, dim3((it.nsim + 63) / 64), dim3(64), 0, s, sims, it.nsim);
+      if (mode == 0) hipLaunchKernelGGL(k_advance, dim3((it.nsim + 63) / 64), dim3(64), 0, s, sims, it.nsim, 1);
       break;
   }
 }
@@ -559,12 +561,17 @@ hipError_t launch_phase(int storage, const SimDev* sims, const Items& it, int ph
   return hipGetLastError();
 }
 
-hipError_t launch_step(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
-  for (int ph = 0; ph < kNumPhases; ++ph) {
-    hipError_t e = launch_phase(storage, sims, it, ph, mode, s);
-    if (e != hipSuccess) return e;
+hipError_t launch_steps(int storage, const SimDev* sims, const Items& it, int steps, int mode, hipStream_t s) {
+  for (int k = 0; k < steps; ++k) {
+    Items ik = it;
+    ik.sub = k;
+    for (int ph = 0; ph < kPhaseAdvance; ++ph) {
+      hipError_t e = launch_phase(storage, sims, ik, ph, mode, s);
+      if (e != hipSuccess) return e;
+    }
   }
-  return hipSuccess;
+  if (mode == 0) hipLaunchKernelGGL(k_advance, dim3((it.nsim + 63) / 64), dim3(64), 0, s, sims, it.nsim, steps);
+  return hipGetLastError();
 }
 
 hipError_t launch_reduce(int storage, const SimDev* sims, const Items& it, hipStream_t s) {

@@ -226,7 +226,7 @@ ibl_status capture(int storage, const SimDev* sims, const Items& it, hipStream_t
   hipGraph_t graph = nullptr;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
   hipError_t le = hipSuccess;
-  for (int k = 0; k < steps && le == hipSuccess; ++k) le = launch_step(storage, sims, it, 0, s);
+  le = launch_steps(storage, sims, it, steps, 0, s);
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
     if (graph) hipGraphDestroy(graph);
@@ -297,6 +297,7 @@ ibl_status upload_simdev(ibl_sim S) {
   it.cube_off = S->ditems + 6;
   it.big_templates = S->big_templates;
   it.forces_variant = forces_variant();
+  it.sub = 0;
   drop_graphs(S->g1, S->gN);
   return IBL_OK;
 }
@@ -614,7 +615,7 @@ ibl_status ibl_sync(ibl_sim S) {
 
 static ibl_status observe(ibl_sim S) {
   hipSetDevice(S->device);
-  HIPCHK(launch_step(S->desc.storage, S->dd, S->items, 1, S->stream));
+  HIPCHK(launch_steps(S->desc.storage, S->dd, S->items, 1, 1, S->stream));
   HIPCHK(hipStreamSynchronize(S->stream));
   return IBL_OK;
 }
@@ -852,6 +853,7 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.big_templates = 0;
   for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
   it.forces_variant = forces_variant();
+  it.sub = 0;
   *out = B;
   return IBL_OK;
 }
