@@ -337,6 +337,88 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
   }
 }
 
+// ------------------------------------------------ forces (fixed point) --
+// FP32 / FP16 storage.  Each edge's spring and bending shares (FP64) are added
+// to per-node accumulators in LDS as 64-bit fixed-point integers in units of
+// 2^-kFxBits.  Integer addition is associative, so a node's sum does not
+// depend on the order in which its edges land, and the fourth share of an
+// edge is formed in integers as minus the other three, so the membrane's
+// internal forces sum to exactly zero.  A share component is limited to
+// kFxLimit in magnitude (flagged in the health word beyond it); a node meets
+// at most 16 shares on these templates, so a sum stays below 2^(63-kFxBits).
+// 23 KB of LDS per capsule: several 256-thread workgroups share a CU, so the
+// capsules of a dense suspension run at once instead of in rounds.
+constexpr int kFxThreads = 256;
+constexpr int kFxBits = 50;          // resolution 2^-50 (8.9e-16)
+constexpr double kFxLimit = 128.0;   // |share component| limit, lattice units
+
+__device__ __forceinline__ long long fx_quant(const SimDev& S, double v) {
+  if (!(fabs(v) < kFxLimit)) {
+    atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
+    v = isnan(v) ? 0.0 : copysign(kFxLimit, v);
+  }
+  return (long long)rint(v * 0x1p50);
+}
+
+__device__ __forceinline__ void fx_add(long long* p, long long v) {
+  atomicAdd((unsigned long long*)p, (unsigned long long)v);
+}
+
+__global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __restrict__ sims, Items it, int mode) {
+  static_assert(kFxBits == 50, "fx_quant and the readout scale by 2^50");
+  __shared__ long long acc[3][kLdsNodes];
+  __shared__ BinTable bt;
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    const int m = item - it.mesh_off[s];
+    const int tm = S.mesh_tmpl[m];
+    const int off = S.mesh_off[m];
+    const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
+    const int nn = S.t_nn[tm], ne = S.t_ne[tm];
+    const int e0 = S.t_edge0[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const GLB double* X0 = S.X + off;
+    for (int i = tid; i < nn; i += kFxThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
+    __syncthreads();
+    for (int e = tid; e < ne; e += kFxThreads) {
+      const GLB int* v = S.ev + 4 * (e0 + e);
+      int vk[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) vk[k] = v[k];
+      D3 p[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) p[k] = {X0[vk[k]], X0[ms + vk[k]], X0[2 * ms + vk[k]]};
+      D3 G0, G3, F1;
+      edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
+      const double g0[3] = {G0.x, G0.y, G0.z}, g3[3] = {G3.x, G3.y, G3.z}, f1[3] = {F1.x, F1.y, F1.z};
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const long long q0 = fx_quant(S, g0[a]), q3 = fx_quant(S, g3[a]), q1 = fx_quant(S, f1[a]);
+        fx_add(&acc[a][vk[0]], q0);
+        fx_add(&acc[a][vk[1]], q1);
+        fx_add(&acc[a][vk[2]], -(q0 + q1 + q3));
+        fx_add(&acc[a][vk[3]], q3);
+      }
+    }
+    __syncthreads();
+    for (int i0 = 0; i0 < nn; i0 += kFxThreads) {  // uniform: emit_nodes holds barriers
+      const int i = i0 + tid;
+      const bool act = i < nn;
+      double F[3], Xp[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        F[a] = act ? (double)acc[a][i] * 0x1p-50 : 0.0;
+        Xp[a] = act ? X0[a * ms + i] : 0.0;
+      }
+      emit_nodes<float>(S, bt, act, off + i, Xp, F, mode);
+    }
+    __syncthreads();  // accumulators read before the next capsule clears them
+  }
+}
+
 // ------------------------------------------------ forces (edge / node split) --
 // k_edge_forces: every edge of every capsule at once -- its spring and bending
 // shares on its four vertices (FP64) go to a scratch slot, 3 * (first node of
@@ -576,6 +658,9 @@ void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
                        sims, it, mode);
     hipLaunchKernelGGL(k_node_forces<R>, dim3(grid_for(it.mesh_total * kNodeChunks, 1 << 20)), dim3(256), 0,
                        s, sims, it, mode);
+  } else if (sizeof(R) == 4 && it.forces_variant == 0) {
+    hipLaunchKernelGGL(k_forces_fx, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kFxThreads), 0, s, sims, it,
+                       mode);
   } else {
     hipLaunchKernelGGL(k_forces_lds<R>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(forces_threads<R>()), 0, s,
                        sims, it, mode);

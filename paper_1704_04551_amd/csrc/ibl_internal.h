@@ -59,6 +59,7 @@ enum Health : uint32_t {
   kHNodeRange = 0x8u,
   kHOverflow = 0x10u,
   kHNonfiniteX = 0x20u,
+  kHForceRange = 0x40u,
 };
 
 // Spreading record of one node, written by the force kernel at X^n and read by
@@ -154,7 +155,8 @@ struct Items {
   int32_t mesh_total;        // capsules
   int32_t cube_total;        // home cubes of simulations with capsules (interpolation) (interpolation)
   int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
-  int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels
+  int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels,
+                             // 2: FP32 / FP16 storage through the edge-share LDS kernel
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;

@@ -62,7 +62,9 @@ int log2i(int v) {
 
 int forces_variant() {
   const char* v = getenv("IBL_FORCES");
-  return (v && strcmp(v, "split") == 0) ? 1 : 0;
+  if (v && strcmp(v, "split") == 0) return 1;
+  if (v && strcmp(v, "shares") == 0) return 2;
+  return 0;
 }
 
 size_t align_up(size_t v, size_t a = 256) { return (v + a - 1) / a * a; }
@@ -303,7 +305,7 @@ ibl_status upload_simdev(ibl_sim S) {
 }
 
 ibl_status health_status(uint32_t h) {
-  if (h & (kHNonfiniteF | kHRho | kHNonfiniteX))
+  if (h & (kHNonfiniteF | kHRho | kHNonfiniteX | kHForceRange))
     return fail(IBL_ERR_UNSTABLE, "simulation became unstable (health word 0x" + std::to_string(h) + ")");
   if (h & (kHNodeRange | kHOverflow))
     return fail(IBL_ERR_STATE, "node outside the admissible range or candidate overflow (health 0x" +

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(HERE, "libibl.so")
 STORAGE = {"f64": 0, "f32": 1, "f16": 2}
 DELTA = {"cos": 0, "peskin4": 1}
 HEALTH_BITS = {0x1: "nonfinite-f", 0x2: "rho", 0x4: "mach", 0x8: "node-range", 0x10: "overflow",
-               0x20: "nonfinite-x"}
+               0x20: "nonfinite-x", 0x40: "force-range"}
 
 
 class IBLError(RuntimeError):
