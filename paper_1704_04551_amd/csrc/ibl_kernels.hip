@@ -208,21 +208,54 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
 // (below the rounding of one share in the compute precision); headroom 2^4
 // (31 - 27, 63 - 58) times max|F| per cell, while the delta kernel's
 // partition of unity bounds a cell's sum by max|F| times the nodes per cell.
+//
+// FP32 / FP16: the x and y sums share one 64-bit word, y 2^32 + x, so one
+// 64-bit atomic adds both (z takes a 32-bit one).  The word's sum is exactly
+// (sum y) 2^32 + (sum x); the low 32 bits, sign-extended, give sum x as long
+// as it fits in 32 bits (the headroom above), and the rest gives sum y.
 template <typename R>
 struct FixAcc;
 template <>
 struct FixAcc<float> {
-  using A = int32_t;
   static constexpr int kBits = 27;
-  __device__ static A fix(float v) { return __float2int_rn(v); }
-  __device__ static void add(A* p, A v) { atomicAdd(p, v); }
+  struct Field {
+    long long xy[kBrickCells];
+    int32_t z[kBrickCells];
+  };
+  __device__ static void clear(Field& f, int li) {
+    f.xy[li] = 0;
+    f.z[li] = 0;
+  }
+  __device__ static void add(Field& f, int li, float gx, float gy, float gz) {
+    const long long w = (long long)__float2int_rn(gy) * 4294967296LL + (long long)__float2int_rn(gx);
+    atomicAdd((unsigned long long*)&f.xy[li], (unsigned long long)w);
+    atomicAdd(&f.z[li], __float2int_rn(gz));
+  }
+  __device__ static void get(const Field& f, int li, float inv, float& gx, float& gy, float& gz) {
+    const long long w = f.xy[li];
+    const long long lo = (long long)(int32_t)(uint32_t)w;
+    gx = (float)lo * inv;
+    gy = (float)((w - lo) >> 32) * inv;
+    gz = (float)f.z[li] * inv;
+  }
 };
 template <>
 struct FixAcc<double> {
-  using A = long long;
   static constexpr int kBits = 58;
-  __device__ static A fix(double v) { return __double2ll_rn(v); }
-  __device__ static void add(A* p, A v) { atomicAdd((unsigned long long*)p, (unsigned long long)v); }
+  struct Field {
+    long long c[3][kBrickCells];
+  };
+  __device__ static void clear(Field& f, int li) { f.c[0][li] = f.c[1][li] = f.c[2][li] = 0; }
+  __device__ static void add(Field& f, int li, double gx, double gy, double gz) {
+    atomicAdd((unsigned long long*)&f.c[0][li], (unsigned long long)__double2ll_rn(gx));
+    atomicAdd((unsigned long long*)&f.c[1][li], (unsigned long long)__double2ll_rn(gy));
+    atomicAdd((unsigned long long*)&f.c[2][li], (unsigned long long)__double2ll_rn(gz));
+  }
+  __device__ static void get(const Field& f, int li, double inv, double& gx, double& gy, double& gz) {
+    gx = (double)f.c[0][li] * inv;
+    gy = (double)f.c[1][li] * inv;
+    gz = (double)f.c[2][li] * inv;
+  }
 };
 
 // FP32: registers capped for 5 waves per SIMD (measured best; 6 spills); FP16
@@ -233,8 +266,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
   using FA = FixAcc<R>;
-  using A = typename FA::A;
-  __shared__ A gq[3][kBrickCells];
+  __shared__ typename FA::Field gq;
   // home-cube lists: the brick's home candidates (base cell inside the brick)
   // counted per cube (a brick meets at most 4 cubes: 64 x 4 -> 4 x 1,
   // 32 x 8 -> 2 x 1, 16 x 16 -> 1 x 2)
@@ -264,8 +296,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
       NodeRec<R> q;
       if (tid < cnt) q = *(const NodeRec<R>*)(rec + list[tid]);
 #pragma unroll
-      for (int k = 0; k < kBrickZ; ++k) gq[0][tid + kBrickThreads * k] = gq[1][tid + kBrickThreads * k] =
-          gq[2][tid + kBrickThreads * k] = (A)0;
+      for (int k = 0; k < kBrickZ; ++k) FA::clear(gq, tid + kBrickThreads * k);
       if (tid < 4) hc[tid] = 0;
       // cubes the brick meets: nlx along x by (at most 2) along y
       const int nlx = bx >> kCubeShift[0] > 0 ? bx >> kCubeShift[0] : 1;
@@ -307,10 +338,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
             for (int dx = 0; dx < 4; ++dx) {
               if (!((mx >> dx) & 1)) continue;
               const R wx = w3[0][dx];
-              const int li = row + lx[dx];
-              FA::add(&gq[0][li], FA::fix(gx * wx));
-              FA::add(&gq[1][li], FA::fix(gy * wx));
-              FA::add(&gq[2][li], FA::fix(gz * wx));
+              FA::add(gq, row + lx[dx], gx * wx, gy * wx, gz * wx);
             }
           }
         }
@@ -371,11 +399,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(c
           if (kCz[q]) jz += kCz[q] > 0 ? h[q] : -h[q];
         }
         R gix = (R)0, giy = (R)0, giz = (R)0;  // spread force g_IB
-        if (ib) {
-          gix = (R)gq[0][li] * inv;
-          giy = (R)gq[1][li] * inv;
-          giz = (R)gq[2][li] * inv;
-        }
+        if (ib) FA::get(gq, li, inv, gix, giy, giz);
         const R gx = (R)S.gb[0] + gix, gy = (R)S.gb[1] + giy, gz = (R)S.gb[2] + giz;
         const R rho = (R)1 + drho;
         const R irho = (R)1 / rho;
