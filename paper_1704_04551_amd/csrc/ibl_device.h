@@ -240,11 +240,23 @@ template <>
 __device__ __forceinline__ void delta_weights_r<double>(int kind, double d, double w[4]) {
   delta_weights(kind, d, w);
 }
+// sin and cos of t = pi d / 2 for 0 <= d <= 1 from their Taylor series about
+// 0, through t^11 and t^12: truncation below 6e-8 and 7e-9 on [0, pi/2];
+// evaluated in float, within 2e-7 of the exact values.  A general sincosf
+// carries range reduction this argument never needs.
+__device__ __forceinline__ void sincos_quarter(float d, float& s, float& c) {
+  const float t = 1.5707963267948966f * d, u = t * t;
+  s = t * (1.0f + u * (-1.0f / 6 + u * (1.0f / 120 + u * (-1.0f / 5040 + u * (1.0f / 362880 +
+                                                                                   u * (-1.0f / 39916800))))));
+  c = 1.0f + u * (-0.5f + u * (1.0f / 24 + u * (-1.0f / 720 + u * (1.0f / 40320 + u * (-1.0f / 3628800 +
+                                                                                      u * (1.0f / 479001600))))));
+}
+
 template <>
 __device__ __forceinline__ void delta_weights_r<float>(int kind, float d, float w[4]) {
   if (kind == kCos) {
     float s, c;
-    sincosf(1.5707963267948966f * d, &s, &c);
+    sincos_quarter(d, s, c);
     w[0] = 0.25f * (1.0f - s);
     w[1] = 0.25f * (1.0f + c);
     w[2] = 0.25f * (1.0f + s);
