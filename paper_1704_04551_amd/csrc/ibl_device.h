@@ -21,24 +21,30 @@ namespace {
 // and a body-force increment of 1e-6 added to f_i ~ 0.05 would lose most of
 // its bits in binary32.  Offsets keep them.  FP16 stores h_i as binary16
 // (round to nearest even); FP32 and FP64 store it at full width.
+//
+// A step reads each stored population once and writes each once, and the
+// next read comes a whole step later, after more traffic than the caches
+// hold: the timestep's population loads and stores are non-temporal, so the
+// caches keep what is re-read within the step (the velocity tiles of the
+// interpolation, the spreading records and candidate lists).
 template <int ST>
 struct Store;
 template <>
 struct Store<kF64> {
   using T = double;
   using R = double;
-  __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
+  __device__ static R h(const GLB T* p, int64_t i, int) { return __builtin_nontemporal_load(p + i); }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { p[i] = hq; }
+  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { __builtin_nontemporal_store(hq, p + i); }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return p[i]; }
 };
 template <>
 struct Store<kF32> {
   using T = float;
   using R = float;
-  __device__ static R h(const GLB T* p, int64_t i, int) { return p[i]; }
+  __device__ static R h(const GLB T* p, int64_t i, int) { return __builtin_nontemporal_load(p + i); }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { p[i] = hq; }
+  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { __builtin_nontemporal_store(hq, p + i); }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)p[i]; }
 };
 template <>
@@ -47,7 +53,7 @@ struct Store<kF16> {
   using R = float;
   // binary16 moved as its 16 bits
   __device__ static R h(const GLB T* p, int64_t i, int) {
-    return __half2float(__ushort_as_half(((const GLB unsigned short*)p)[i]));
+    return __half2float(__ushort_as_half(__builtin_nontemporal_load((const GLB unsigned short*)p + i)));
   }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) {
     ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(hq));
@@ -68,7 +74,8 @@ struct Store<kF16> {
     // subnormal, zero and out-of-range values round to nearest
     const bool normal = a >= 0x38800000u && a < 0x477fe000u;
     const uint32_t t = ((a + (r & 0x1fffu)) & ~0x1fffu) | (b & 0x80000000u);
-    ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(normal ? __uint_as_float(t) : hq));
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(normal ? __uint_as_float(t) : hq)),
+                                (GLB unsigned short*)p + i);
   }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
 };
