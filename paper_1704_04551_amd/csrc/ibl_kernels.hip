@@ -258,10 +258,11 @@ struct FixAcc<double> {
   }
 };
 
-// FP32: registers capped for 5 waves per SIMD (measured best; 6 spills); FP16
-// (stochastic rounding) spills under that cap and runs best uncapped
+// FP32 / FP16: registers capped for 5 waves per SIMD (measured best: the
+// spreading phase of one brick hides behind the streaming of the others; FP16
+// spills one register under the cap and still gains)
 template <int ST>
-__global__ __launch_bounds__(kBrickThreads, ST == kF32 ? 5 : 1) void k_lattice(const SimDev* __restrict__ sims,
+__global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
