@@ -344,20 +344,24 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
 // depend on the order in which its edges land, and the fourth share of an
 // edge is formed in integers as minus the other three, so the membrane's
 // internal forces sum to exactly zero.  A share component is limited to
-// kFxLimit in magnitude (flagged in the health word beyond it); a node meets
-// at most 16 shares on these templates, so a sum stays below 2^(63-kFxBits).
+// kFxLimit = 1 lattice unit in magnitude (flagged in the health word beyond
+// it: a force that large is far past any stable lattice-Boltzmann state); a
+// node meets at most 16 shares on these templates, so a sum stays below
+// 2^(63-kFxBits).  With |v 2^50| < 2^51 the rounding to an integer is one FMA:
+// v 2^50 + 1.5 2^52 rounds to an integer of the binade [2^52, 2^53), whose
+// bit pattern minus that of 1.5 2^52 is round(v 2^50).
 // 23 KB of LDS per capsule: several 256-thread workgroups share a CU, so the
 // capsules of a dense suspension run at once instead of in rounds.
 constexpr int kFxThreads = 256;
 constexpr int kFxBits = 50;          // resolution 2^-50 (8.9e-16)
-constexpr double kFxLimit = 128.0;   // |share component| limit, lattice units
+constexpr double kFxLimit = 1.0;     // |share component| limit, lattice units
 
 __device__ __forceinline__ long long fx_quant(const SimDev& S, double v) {
   if (!(fabs(v) < kFxLimit)) {
     atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
     v = isnan(v) ? 0.0 : copysign(kFxLimit, v);
   }
-  return (long long)rint(v * 0x1p50);
+  return __double_as_longlong(fma(v, 0x1p50, 0x1.8p52)) - __double_as_longlong(0x1.8p52);
 }
 
 __device__ __forceinline__ void fx_add(long long* p, long long v) {
