@@ -25,8 +25,9 @@ Prints one JSON line.
 * ``served``: a Poisson stream of Jeffery-orbit jobs through the serving loop
   (continuous batching) and, on the same stream, one job at a time (the
   plain form): p50/p99 latency and aggregate MLUPS of each.
-* ``autotune``: the lattice brick width is timed for 16 / 32 / 64 cells on the
-  workload first (``--no-autotune`` or ``--brick-x`` to skip).
+* ``autotune``: the lattice brick width (16 / 32 / 64 cells) and the
+  candidate-list skin (0 / 1 cell) are timed on the workload first
+  (``--no-autotune``, or ``--brick-x`` with ``--skin``, to skip).
 """
 from __future__ import annotations
 
@@ -46,10 +47,11 @@ HBM_PEAK_GBS = 8000.0
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2}
 
 
-def lattice_traffic(storage, brick_x):
+def lattice_traffic(storage, brick_x, skin):
     """Counter-measured HBM bytes of one collide-stream launch, from the
-    committed profiler summary of this workload, if the kernel sources and the
-    brick width are still the ones it was measured with (else None)."""
+    committed profiler summary of this workload, if the kernel sources, the
+    brick width and the skin are still the ones it was measured with (else
+    None)."""
     import hashlib
     import re
     path = os.path.join(ROOT, "profiles", "k_lattice_rbc_channel_256x128x128_%s_traffic.md" % storage)
@@ -59,7 +61,8 @@ def lattice_traffic(storage, brick_x):
     m_b = re.search(r"^traffic_bytes_k_lattice: (\d+)$", text, re.M)
     m_h = re.search(r"^source_sha256: ([0-9a-f]{64})$", text, re.M)
     m_w = re.search(r"^brick_x: (\d+)$", text, re.M)
-    if not (m_b and m_h and m_w) or int(m_w.group(1)) != brick_x:
+    m_s = re.search(r"^skin: (\d+)$", text, re.M)
+    if not (m_b and m_h and m_w and m_s) or int(m_w.group(1)) != brick_x or int(m_s.group(1)) != skin:
         return None
     csrc = os.path.join(ROOT, "paper_1704_04551_amd", "csrc")
     src = b"".join(open(os.path.join(csrc, f), "rb").read()
@@ -301,9 +304,12 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--no-autotune", action="store_true", help="use the built-in brick width")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the built-in brick width and no skin (or --brick-x / --skin)")
     ap.add_argument("--brick-x", type=int, default=0, choices=[0, 16, 32, 64],
                     help="fixed brick width (skips the autotuner)")
+    ap.add_argument("--skin", type=int, default=None, choices=[0, 1],
+                    help="fixed candidate-list skin (skips the autotuner)")
     ap.add_argument("--batched-steps", type=int, default=500)
     ap.add_argument("--serve-seconds", type=float, default=15.0, help="0 skips the served runs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -344,15 +350,17 @@ def main():
     _log("generating workload")
     spec = load_spec(args)
     tuned = None
-    brick_x = args.brick_x
-    if not brick_x and not args.no_autotune:
-        from paper_1704_04551_amd.autotune import tune_brick_x
-        _log("autotuning the brick width")
-        brick_x, timings = tune_brick_x(spec, args.storage, steps=30, warmup=5, use_memo=False)
-        tuned = {"brick_x": brick_x, "ms_per_step": {str(k): round(v, 4) for k, v in timings.items()}}
+    brick_x, skin = args.brick_x, args.skin
+    if not brick_x and skin is None and not args.no_autotune:
+        from paper_1704_04551_amd.autotune import shape_key, tune
+        _log("autotuning the brick width and list skin")
+        (brick_x, skin), timings = tune(spec, args.storage, steps=30, warmup=5, use_memo=False)
+        tuned = {"brick_x": brick_x, "skin": skin,
+                 "ms_per_step": {shape_key(k): round(v, 4) for k, v in timings.items()}}
         _log("autotune: %s" % tuned)
+    skin = skin or 0
     _log("%d cells, %d nodes; creating simulation" % (len(spec.capsules), spec.nodes))
-    sim = ibl.Sim.from_spec(spec, storage=args.storage, device="cuda:0", brick_x=brick_x)
+    sim = ibl.Sim.from_spec(spec, storage=args.storage, device="cuda:0", brick_x=brick_x, skin=skin)
     sim.step(args.warmup)
     sim.sync()
     _log("warmup done")
@@ -398,11 +406,12 @@ def main():
         "roofline": {"bound": "hbm", "kernel": "k_lattice (collide-stream)",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": lattice_traffic(args.storage, brick_x or 64),
+                     "traffic": lattice_traffic(args.storage, brick_x or 64, skin),
                      "bytes_per_launch": lat_bytes, "launch_ms": round(lat_ms, 5)},
         "step_roofline_frac": round(cells * 2 * 19 * sb / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
         "phase_ms": {k: round(v, 5) for k, v in phases.items()},
         "brick_x": brick_x or None,
+        "skin": skin,
         "autotune": tuned,
         "health": health,
     }

@@ -100,8 +100,13 @@ typedef struct {
   int32_t brick_x;         /* lattice brick width along x: 16, 32 or 64 cells (bricks are
                               brick_x x 256/brick_x x 4 cells, one workgroup each), or 0
                               for the widest that the x extent fills.  A tuning knob:
-                              results agree to the spreading's fixed-point resolution,
-                              not bitwise, across widths. */
+                              results are bitwise identical across widths. */
+  int32_t skin;            /* candidate lists of the spreading (node binning): 0 rebuilds
+                              them every step; 1 builds them with a one-cell skin around
+                              each node's stencil and rebuilds only after some node's
+                              stencil base has moved more than one cell from where it was
+                              at the last build.  A tuning knob: results are bitwise
+                              identical either way. */
 } ibl_sim_desc;
 
 typedef struct ibl_sim_s* ibl_sim;
@@ -117,7 +122,7 @@ ibl_status ibl_sim_bytes(const ibl_sim_desc* desc, size_t* out_bytes);
  * populations to equilibrium at rho = 1 and the initial velocity (Sec. 2.1).
  * hip_stream: the hipStream_t to run on, or NULL for a stream the library
  * creates (non-blocking, default priority) and destroys.
- * Errors: IBL_ERR_ARG (tau <= 1/2, n < 4 or > 32767, bad enums, brick_x not
+ * Errors: IBL_ERR_ARG (tau <= 1/2, n < 4 or > 32767, bad enums, skin not 0 or 1, brick_x not
  * 0/16/32/64, 2 x cells x element bytes >= 4 GiB), IBL_ERR_NOMEM (arena too
  * small), IBL_ERR_DEVICE. */
 ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t arena_bytes,

@@ -292,6 +292,14 @@ __device__ __forceinline__ void rec_weights(const NodeRec<float>& q, int kind, f
 }
 
 
+// Both list buffers empty (buffer 0 in use), both step parities marked to
+// rebuild, no force maximum recorded.
+__device__ __forceinline__ void reset_list_control(const SimDev& S) {
+  S.lctl[0] = S.lctl[1] = 0;
+  S.lctl[2] = S.lctl[3] = 1;
+  S.fmax[0] = S.fmax[1] = 0u;
+}
+
 __device__ __forceinline__ bool solid_cell(const SimDev& S, int x, int y, int z) {
   return (S.wall[0] && (x == 0 || x == S.n[0] - 1)) || (S.wall[1] && (y == 0 || y == S.n[1] - 1)) ||
          (S.wall[2] && (z == 0 || z == S.n[2] - 1));

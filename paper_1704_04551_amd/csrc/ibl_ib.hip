@@ -22,28 +22,6 @@
 namespace ibl {
 namespace {
 
-// The bricks a node's stencil touches.  Along an axis the four stencil cells
-// are consecutive (modulo n) and bricks are at least four cells long, so they
-// meet one or two bricks, a third only on a periodic axis whose last brick is
-// one to three cells long.  Combination
-// k = ix + 2 iy + 4 iz takes the first (0) or second (1) brick of each axis.
-struct NodeBricks {
-  int br[8];
-  int mask;     // bit k: combination k exists
-  int rare;     // an axis meets a third brick: the node is appended directly
-  int base[3];  // the stencil base cell (periodic axes wrapped)
-};
-
-// brick index along one axis of the four stencil cells from `base`
-__device__ __forceinline__ void axis_bricks(int base, int n, int wall, int shift, int b[4]) {
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    int c = base - 1 + k;
-    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
-    b[k] = c >> shift;
-  }
-}
-
 // Store a node's spreading record (see NodeRec).
 __device__ __forceinline__ void write_record(const SimDev& S, int gid, const int base[3], int valid,
                                              const double d[3], const double Fv[3]) {
@@ -71,21 +49,20 @@ __device__ __forceinline__ void write_record(const SimDev& S, int gid, const int
   *(NodeRec<float>*)((GLB NodeRec<float>*)S.rec + gid) = q;
 }
 
-// Spreading record and validity check of one node; fills the bricks its
-// stencil touches.
+// Spreading record and validity check of one node (base cell, validity).
 // The node arrays F and U are outputs of observation only (mode 1): a step
 // (mode 0) passes forces to spreading through the records and velocities to
 // the node update in registers.
 template <typename R>
-__device__ void make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3],
-                            NodeBricks& nb, int mode) {
+__device__ void make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3], int base[3],
+                            int& valid, int mode) {
   const int64_t ms = (int64_t)S.maxn;
   if (mode == 1) {
     S.F[gid] = Fv[0];
     S.F[ms + gid] = Fv[1];
     S.F[2 * ms + gid] = Fv[2];
   }
-  int valid = 1;
+  valid = 1;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(Xp[a])) {
@@ -96,7 +73,6 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
       atomicOr((unsigned*)S.health, (uint32_t)kHNodeRange);
     }
   }
-  int base[3];
   R d[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -106,19 +82,127 @@ __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const 
     d[a] = (R)(valid ? Xp[a] - fb : 0.0);
   }
   write_record(S, gid, base, valid, d, Fv);
+  if (!valid && mode == 1) {  // on no candidate list: interpolation never visits it
+    S.U[gid] = 0.0;
+    S.U[ms + gid] = 0.0;
+    S.U[2 * ms + gid] = 0.0;
+  }
+}
+
+// The bricks along one axis met by cells base-1-w .. base+2+w (the stencil
+// widened by a skin of w cells): `cnt` consecutive bricks from `first`, modulo
+// the axis's brick count on a periodic axis (the cells wrap; a short axis
+// may be covered whole); clipped to the lattice on a wall axis.
+__device__ __forceinline__ void skin_bricks(int base, int n, int wall, int shift, int nb, int w, int& first,
+                                            int& cnt) {
+  const int kW = 4 + 2 * w;
+  const int lo = base - 1 - w;
+  if (wall) {
+    const int c0 = lo < 0 ? 0 : lo, c1 = lo + kW - 1 < n ? lo + kW - 1 : n - 1;
+    first = c0 >> shift;
+    cnt = (c1 >> shift) - first + 1;
+    return;
+  }
+  const int mask = (1 << shift) - 1;
+  int c = ((lo % n) + n) % n;
+  first = c >> shift;
+  cnt = 1;
+  for (int k = 1; k < kW; ++k) {  // a brick starts where the cell index is a multiple
+    c = c + 1 == n ? 0 : c + 1;   // of the brick size, or wraps to 0
+    cnt += (c & mask) == 0;
+  }
+  cnt = cnt < nb ? cnt : nb;
+}
+
+// Append a node to the candidate list (buffer `buf`) of every brick its
+// skin-widened stencil meets.  One device-scope atomic per (node, brick): a
+// rebuild happens only when some node has moved a skin's width.
+__device__ void append_skin(const SimDev& S, int buf, const int base[3], int gid) {
+  int f[3], c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) skin_bricks(base[a], S.n[a], S.wall[a], S.bsh[a], S.nb[a], S.skin, f[a], c[a]);
+  const int64_t b0 = (int64_t)buf * S.nbrick;
+  for (int jz = 0; jz < c[2]; ++jz) {
+    const int bz = f[2] + jz < S.nb[2] ? f[2] + jz : f[2] + jz - S.nb[2];
+    for (int jy = 0; jy < c[1]; ++jy) {
+      const int by = f[1] + jy < S.nb[1] ? f[1] + jy : f[1] + jy - S.nb[1];
+      for (int jx = 0; jx < c[0]; ++jx) {
+        const int bx = f[0] + jx < S.nb[0] ? f[0] + jx : f[0] + jx - S.nb[0];
+        const int64_t br = b0 + bx + S.nb[0] * (by + (int64_t)S.nb[1] * bz);
+        const int pos = atomicAdd((int*)&S.bcount[br], 1);
+        if (pos < kCandCap) S.blist[br * kCandCap + pos] = gid;
+      }
+    }
+  }
+}
+
+// List state of a simulation's current step, read by the force kernels:
+// rebuild flag (always without a skin; an observation always builds its own
+// lists, into the free buffer) and the buffer this step's lists are in.
+struct ListStep {
+  int par, rb, buf;
+};
+__device__ __forceinline__ ListStep list_step(const SimDev& S, const Items& it, int mode) {
+  ListStep L;
+  L.par = (int)((*S.step + it.sub) & 1);
+  L.rb = mode == 1 || S.skin == 0 ? 1 : S.lctl[2 + L.par];
+  L.buf = S.lctl[L.par ^ 1] ^ L.rb;
+  return L;
+}
+
+// Skin lists: record of one node; on a rebuild its build-time base cell and
+// its list entries.  `fbits` collects the largest force component (float bits).
+template <typename R>
+__device__ void emit_node(const SimDev& S, const ListStep& L, int gid, const double Xp[3], const double Fv[3],
+                          int mode, uint32_t& fbits) {
+  int base[3], valid;
+  make_record<R>(S, gid, Xp, Fv, base, valid, mode);
+  const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
+  const uint32_t fb = __float_as_uint(isfinite(fm) ? fm : 0.f);
+  fbits = fb > fbits ? fb : fbits;
+  if (!L.rb || !valid) return;
+  if (mode == 0) {
+    GLB int16_t* q = S.bb0 + 4 * (int64_t)gid;
+    q[0] = (int16_t)base[0];
+    q[1] = (int16_t)base[1];
+    q[2] = (int16_t)base[2];
+  }
+  append_skin(S, L.buf, base, gid);
+}
+
+
+// Without a skin: the bricks a node's stencil touches.  Along an axis the four stencil cells
+// are consecutive (modulo n) and bricks are at least four cells long, so they
+// meet one or two bricks, a third only on a periodic axis whose last brick is
+// one to three cells long.  Combination
+// k = ix + 2 iy + 4 iz takes the first (0) or second (1) brick of each axis.
+struct NodeBricks {
+  int br[8];
+  int mask;     // bit k: combination k exists
+  int rare;     // an axis meets a third brick: the node is appended directly
+  int base[3];  // the stencil base cell (periodic axes wrapped)
+};
+
+// brick index along one axis of the four stencil cells from `base`
+__device__ __forceinline__ void axis_bricks(int base, int n, int wall, int shift, int b[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    int c = base - 1 + k;
+    if (!wall) c = c < 0 ? c + n : (c >= n ? c - n : c);
+    b[k] = c >> shift;
+  }
+}
+
+
+// The bricks of a node's stencil from its base cell (none when the node is
+// not valid).
+__device__ __forceinline__ void node_bricks(const SimDev& S, const int base[3], int valid, NodeBricks& nb) {
   nb.mask = 0;
   nb.rare = 0;
   nb.base[0] = base[0];
   nb.base[1] = base[1];
   nb.base[2] = base[2];
-  if (!valid) {  // on no candidate list: interpolation never visits it
-    if (mode == 1) {
-      S.U[gid] = 0.0;
-      S.U[ms + gid] = 0.0;
-      S.U[2 * ms + gid] = 0.0;
-    }
-    return;
-  }
+  if (!valid) return;
   int p0[3], p1[3], h1[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -151,14 +235,12 @@ struct BinTable {
   int key[kBinSlots];
   int cnt[kBinSlots];
   int base[kBinSlots];
-  uint32_t mx[kBinSlots];  // largest |F component| appended to the brick (float bits)
 };
 
 __device__ void bin_clear(BinTable& T) {
   for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x) {
     T.key[i] = -1;
     T.cnt[i] = 0;
-    T.mx[i] = 0u;
   }
 }
 
@@ -172,15 +254,15 @@ __device__ int bin_slot(BinTable& T, int key) {
   return -1;  // table crowded: the caller appends directly
 }
 
-__device__ __forceinline__ void append_one(const SimDev& S, int b, int gid, uint32_t fbits) {
-  atomicMax((unsigned*)&S.bmax[b], fbits);
-  const int pos = atomicAdd((int*)&S.bcount[b], 1);
-  if (pos < kCandCap) S.blist[(int64_t)b * kCandCap + pos] = gid;
+__device__ __forceinline__ void append_one(const SimDev& S, int buf, int b, int gid) {
+  const int64_t br = (int64_t)buf * S.nbrick + b;
+  const int pos = atomicAdd((int*)&S.bcount[br], 1);
+  if (pos < kCandCap) S.blist[br * kCandCap + pos] = gid;
 }
 
 // All threads of the workgroup call this with their node's bricks (mask 0 for
 // an inactive thread).  Contains barriers: uniform control flow required.
-__device__ void bin_append(const SimDev& S, BinTable& T, int gid, const NodeBricks& nb, uint32_t fbits) {
+__device__ void bin_append(const SimDev& S, BinTable& T, int buf, int gid, const NodeBricks& nb) {
   int slot[8], rank[8];
   bin_clear(T);
   __syncthreads();
@@ -190,64 +272,89 @@ __device__ void bin_append(const SimDev& S, BinTable& T, int gid, const NodeBric
     rank[k] = 0;
     if ((nb.mask >> k) & 1) {
       slot[k] = bin_slot(T, nb.br[k]);
-      if (slot[k] >= 0) {
-        rank[k] = atomicAdd(&T.cnt[slot[k]], 1);
-        atomicMax(&T.mx[slot[k]], fbits);
-      }
+      if (slot[k] >= 0) rank[k] = atomicAdd(&T.cnt[slot[k]], 1);
     }
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kBinSlots; i += blockDim.x)
-    if (T.key[i] >= 0) {
-      T.base[i] = atomicAdd((int*)&S.bcount[T.key[i]], T.cnt[i]);
-      atomicMax((unsigned*)&S.bmax[T.key[i]], T.mx[i]);
-    }
+    if (T.key[i] >= 0) T.base[i] = atomicAdd((int*)&S.bcount[(int64_t)buf * S.nbrick + T.key[i]], T.cnt[i]);
   __syncthreads();
 #pragma unroll
   for (int k = 0; k < 8; ++k)
     if ((nb.mask >> k) & 1) {
       if (slot[k] < 0) {
-        append_one(S, nb.br[k], gid, fbits);
+        append_one(S, buf, nb.br[k], gid);
       } else {
         const int pos = T.base[slot[k]] + rank[k];
-        if (pos < kCandCap) S.blist[(int64_t)nb.br[k] * kCandCap + pos] = gid;
+        if (pos < kCandCap) S.blist[((int64_t)buf * S.nbrick + nb.br[k]) * kCandCap + pos] = gid;
       }
     }
   __syncthreads();
 }
 
-// Record + aggregated append of one node per thread (active = false: no node).
-template <typename R>
-__device__ void emit_nodes(const SimDev& S, BinTable& T, bool active, int gid, const double Xp[3],
-                           const double Fv[3], int mode) {
-  NodeBricks nb;
-  nb.mask = 0;
-  nb.rare = 0;
-  if (active) make_record<R>(S, gid, Xp, Fv, nb, mode);
-  // largest force component in the precision the spreading reads (float)
-  const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
-  const uint32_t fbits = __float_as_uint(isfinite(fm) ? fm : 0.f);
-  if (nb.rare) {
-    // every distinct brick: the stencil points first of their brick per axis
-    int bx[4], by[4], bz[4];
-    axis_bricks(nb.base[0], S.n[0], S.wall[0], S.bsh[0], bx);
-    axis_bricks(nb.base[1], S.n[1], S.wall[1], S.bsh[1], by);
-    axis_bricks(nb.base[2], S.n[2], S.wall[2], S.bsh[2], bz);
-    for (int kz = 0; kz < 4; ++kz) {
-      bool fz = true;
-      for (int j = 0; j < kz; ++j) fz &= bz[j] != bz[kz];
-      for (int ky = 0; ky < 4; ++ky) {
-        bool fy = true;
-        for (int j = 0; j < ky; ++j) fy &= by[j] != by[ky];
-        for (int kx = 0; kx < 4; ++kx) {
-          bool fx = true;
-          for (int j = 0; j < kx; ++j) fx &= bx[j] != bx[kx];
-          if (fx && fy && fz) append_one(S, bx[kx] + S.nb[0] * (by[ky] + S.nb[1] * bz[kz]), gid, fbits);
-        }
+
+// A node whose stencil meets a third brick along an axis (short periodic
+// axes): appended directly to every distinct brick.
+__device__ void append_rare(const SimDev& S, int buf, const NodeBricks& nb, int gid) {
+  // every distinct brick: the stencil points first of their brick per axis
+  int bx[4], by[4], bz[4];
+  axis_bricks(nb.base[0], S.n[0], S.wall[0], S.bsh[0], bx);
+  axis_bricks(nb.base[1], S.n[1], S.wall[1], S.bsh[1], by);
+  axis_bricks(nb.base[2], S.n[2], S.wall[2], S.bsh[2], bz);
+  for (int kz = 0; kz < 4; ++kz) {
+    bool fz = true;
+    for (int j = 0; j < kz; ++j) fz &= bz[j] != bz[kz];
+    for (int ky = 0; ky < 4; ++ky) {
+      bool fy = true;
+      for (int j = 0; j < ky; ++j) fy &= by[j] != by[ky];
+      for (int kx = 0; kx < 4; ++kx) {
+        bool fx = true;
+        for (int j = 0; j < kx; ++j) fx &= bx[j] != bx[kx];
+        if (fx && fy && fz) append_one(S, buf, bx[kx] + S.nb[0] * (by[ky] + S.nb[1] * bz[kz]), gid);
       }
     }
   }
-  bin_append(S, T, gid, nb, fbits);
+}
+
+// Lists rebuilt every step: record and aggregated appends of one node per
+// thread (active = false: no node).  Contains barriers: uniform control flow
+// required.
+template <typename R>
+__device__ void emit_nodes(const SimDev& S, BinTable& T, const ListStep& L, bool active, int gid,
+                           const double Xp[3], const double Fv[3], int mode, uint32_t& fbits) {
+  NodeBricks nb;
+  nb.mask = 0;
+  nb.rare = 0;
+  if (active) {
+    int base[3], valid;
+    make_record<R>(S, gid, Xp, Fv, base, valid, mode);
+    const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
+    const uint32_t fb = __float_as_uint(isfinite(fm) ? fm : 0.f);
+    fbits = fb > fbits ? fb : fbits;
+    node_bricks(S, base, valid, nb);
+    if (nb.rare) append_rare(S, L.buf, nb, gid);
+  }
+  bin_append(S, T, L.buf, gid, nb);
+}
+
+// Workgroup maximum of `fbits` into the step's maximum: one device-scope
+// atomic per workgroup, skipped when the recorded value is already larger.
+// Contains a barrier: uniform control flow required.
+__device__ void flush_fmax(const SimDev& S, int par, uint32_t* wmax, uint32_t fbits) {
+  if (fbits) atomicMax(wmax, fbits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t v = *wmax;
+    *wmax = 0u;
+    if (v > __hip_atomic_load(&S.fmax[par], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax((unsigned*)&S.fmax[par], v);
+  }
+}
+
+// The first capsule of a simulation clears the next step's rebuild flag,
+// which interpolation sets when a node leaves its skin.
+__device__ __forceinline__ void clear_next_rebuild(const SimDev& S, const ListStep& L, int m, int mode) {
+  if (mode == 0 && m == 0 && threadIdx.x == 0) S.lctl[2 + (L.par ^ 1)] = 0;
 }
 
 // ------------------------------------------------------------ forces (LDS) --
@@ -294,8 +401,10 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
                                                                     Items it, int mode) {
   __shared__ R pe[9][kLdsEdges];
   __shared__ BinTable bt;
+  __shared__ uint32_t wmax;
   const int tid = threadIdx.x;
   constexpr int NT = forces_threads<R>();
+  if (tid == 0) wmax = 0u;
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
     const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
@@ -308,6 +417,8 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
     const int row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
     const GLB double* X0 = S.X + off;
+    const ListStep L = list_step(S, it, mode);
+    clear_next_rebuild(S, L, m, mode);
     for (int e = tid; e < ne; e += NT) {
       const GLB int* v = S.ev + 4 * (e0 + e);
       D3 p[4];
@@ -331,9 +442,16 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
     gather_node<R>(S, pe, actb ? S.inc_ptr[row0 + ib] : 0, actb ? S.inc_ptr[row0 + ib + 1] : 0, e0, Fb);
     const double Xa[3] = {acta ? X0[ia] : 0.0, acta ? X0[ms + ia] : 0.0, acta ? X0[2 * ms + ia] : 0.0};
     const double Xb[3] = {actb ? X0[ib] : 0.0, actb ? X0[ms + ib] : 0.0, actb ? X0[2 * ms + ib] : 0.0};
-    emit_nodes<R>(S, bt, acta, off + ia, Xa, Fa, mode);
-    if (nn > NT) emit_nodes<R>(S, bt, actb, off + ib, Xb, Fb, mode);  // uniform
-    __syncthreads();  // shares of this capsule read before the next one's are written
+    uint32_t fbits = 0u;
+    if (S.skin == 0) {  // uniform
+      emit_nodes<R>(S, bt, L, acta, off + ia, Xa, Fa, mode, fbits);
+      if (nn > NT) emit_nodes<R>(S, bt, L, actb, off + ib, Xb, Fb, mode, fbits);  // uniform
+    } else {
+      if (acta) emit_node<R>(S, L, off + ia, Xa, Fa, mode, fbits);
+      if (actb) emit_node<R>(S, L, off + ib, Xb, Fb, mode, fbits);
+    }
+    flush_fmax(S, L.par, &wmax, fbits);  // (its barrier also orders this capsule's
+                                         // share reads before the next one's writes)
   }
 }
 
@@ -372,7 +490,9 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
   static_assert(kFxBits == 50, "fx_quant and the readout scale by 2^50");
   __shared__ long long acc[3][kLdsNodes];
   __shared__ BinTable bt;
+  __shared__ uint32_t wmax;
   const int tid = threadIdx.x;
+  if (tid == 0) wmax = 0u;
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
     const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
@@ -385,6 +505,8 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
     const int e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
     const GLB double* X0 = S.X + off;
+    const ListStep L = list_step(S, it, mode);
+    clear_next_rebuild(S, L, m, mode);
     for (int i = tid; i < nn; i += kFxThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
     __syncthreads();
     for (int e = tid; e < ne; e += kFxThreads) {
@@ -408,18 +530,32 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
       }
     }
     __syncthreads();
-    for (int i0 = 0; i0 < nn; i0 += kFxThreads) {  // uniform: emit_nodes holds barriers
-      const int i = i0 + tid;
-      const bool act = i < nn;
-      double F[3], Xp[3];
+    uint32_t fbits = 0u;
+    if (S.skin == 0) {  // uniform
+      for (int i0 = 0; i0 < nn; i0 += kFxThreads) {  // uniform: emit_nodes holds barriers
+        const int i = i0 + tid;
+        const bool act = i < nn;
+        double F[3], Xp[3];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        F[a] = act ? (double)acc[a][i] * 0x1p-50 : 0.0;
-        Xp[a] = act ? X0[a * ms + i] : 0.0;
+        for (int a = 0; a < 3; ++a) {
+          F[a] = act ? (double)acc[a][i] * 0x1p-50 : 0.0;
+          Xp[a] = act ? X0[a * ms + i] : 0.0;
+        }
+        emit_nodes<float>(S, bt, L, act, off + i, Xp, F, mode, fbits);
       }
-      emit_nodes<float>(S, bt, act, off + i, Xp, F, mode);
+    } else {
+      for (int i = tid; i < nn; i += kFxThreads) {
+        double F[3], Xp[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          F[a] = (double)acc[a][i] * 0x1p-50;
+          Xp[a] = X0[a * ms + i];
+        }
+        emit_node<float>(S, L, off + i, Xp, F, mode, fbits);
+      }
     }
-    __syncthreads();  // accumulators read before the next capsule clears them
+    flush_fmax(S, L.par, &wmax, fbits);  // (its barrier: accumulators read before the next
+                                         // capsule clears them)
   }
 }
 
@@ -467,7 +603,9 @@ __global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ 
 template <typename R>
 __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ sims, Items it, int mode) {
   __shared__ BinTable bt;
+  __shared__ uint32_t wmax;
   const int tid = threadIdx.x;
+  if (tid == 0) wmax = 0u;
   for (int item = xcd_block(); item < it.mesh_total * kNodeChunks; item += gridDim.x) {
     const int mi = item / kNodeChunks, c = item % kNodeChunks;
     const int s = find_sim(it.mesh_off, it.nsim, mi);
@@ -479,6 +617,9 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
     const int nn = S.t_nn[tm], row0 = S.t_node0[tm], e0 = S.t_edge0[tm];
     const int64_t ms = (int64_t)S.maxn;
     const GLB double* scr = S.escr + 9 * (3 * (int64_t)off);
+    const ListStep L = list_step(S, it, mode);
+    clear_next_rebuild(S, L, c == 0 ? m : 1, mode);
+    uint32_t fbits = 0u;
     for (int i0 = c * 256; i0 < nn; i0 += 256 * kNodeChunks) {
       const int i = i0 + tid;
       const bool act = i < nn;
@@ -505,8 +646,10 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
       }
       const int gid = off + i;
       const double Xp[3] = {act ? S.X[gid] : 0.0, act ? S.X[ms + gid] : 0.0, act ? S.X[2 * ms + gid] : 0.0};
-      emit_nodes<R>(S, bt, act, gid, Xp, F, mode);
+      if (S.skin == 0) emit_nodes<R>(S, bt, L, act, gid, Xp, F, mode, fbits);  // uniform
+      else if (act) emit_node<R>(S, L, gid, Xp, F, mode, fbits);
     }
+    flush_fmax(S, L.par, &wmax, fbits);
   }
 }
 
@@ -530,7 +673,7 @@ __device__ __forceinline__ int margin_wrap(int c, int n) {
 
 template <typename R>
 __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCubeTile], const NodeRec<R>& q,
-                                            int node, int ox, int oy, int oz, int mode) {
+                                            int node, int ox, int oy, int oz, int mode, int next_par) {
   constexpr int ex = (1 << kCubeShift[0]) + 3, exy = ex * ((1 << kCubeShift[1]) + 3);
   // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
   const int t0 = (q.base[0] - ox) + ex * (q.base[1] - oy) + exy * (q.base[2] - oz);
@@ -553,10 +696,34 @@ __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCube
     }
   const int64_t ms = (int64_t)S.maxn;
   const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
-  if (mode == 0) {
+  if (mode == 0 && S.skin == 0) {
     S.X[node] += ux;
     S.X[ms + node] += uy;
     S.X[2 * ms + node] += uz;
+  } else if (mode == 0) {
+    const double xn[3] = {S.X[node] + ux, S.X[ms + node] + uy, S.X[2 * ms + node] + uz};
+    S.X[node] = xn[0];
+    S.X[ms + node] = xn[1];
+    S.X[2 * ms + node] = xn[2];
+    // the next step rebuilds the candidate lists when the node's stencil base
+    // leaves the skin around its base at the last build
+    const GLB int16_t* b0 = S.bb0 + 4 * (int64_t)node;
+    bool out = false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double fb = floor(xn[a]);
+      if (!(fabs(fb) < 1e9)) {
+        out = true;
+        continue;
+      }
+      int dlt = (int)fb - b0[a];
+      if (!S.wall[a]) {  // periodic: the shortest signed distance modulo n
+        dlt %= S.n[a];
+        dlt = dlt > S.n[a] / 2 ? dlt - S.n[a] : (dlt < -S.n[a] / 2 ? dlt + S.n[a] : dlt);
+      }
+      out |= dlt > S.skin || dlt < -S.skin;
+    }
+    if (out) atomicOr((unsigned*)&S.lctl[2 + next_par], 1u);
   } else {
     S.U[node] = ux;
     S.U[ms + node] = uy;
@@ -575,6 +742,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
     const int s = find_sim(it.cube_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    const int next_par = (int)((*S.step + it.sub + 1) & 1);
     const int64_t h = item - it.cube_off[s];
     int cnt = S.hcount[h];
     if (cnt == 0) continue;  // no node has its base here (uniform)
@@ -641,7 +809,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
           q = *(const NodeRec<R>*)(rec + node);
         }
       }
-      if (node >= 0) interp_node<R>(S, ut, q, node, ox, oy, oz, mode);
+      if (node >= 0) interp_node<R>(S, ut, q, node, ox, oy, oz, mode, next_par);
     }
     __syncthreads();
     if (tid == 0) S.hcount[h] = 0;

@@ -26,6 +26,10 @@ constexpr int kBrickThreads = 256;
 constexpr int kBrickZ = 4;
 constexpr int kBrickCells = kBrickThreads * kBrickZ;
 constexpr int kCandCap = 4096;       // candidate nodes per brick
+// Candidate lists are rebuilt every step (skin 0), or built with a skin of
+// `skin` cells around each node's stencil and kept while every node's stencil
+// base cell stays within `skin` cells (per axis) of its base when the lists
+// were built.
 // Interpolation groups nodes by home cube (the cube of their stencil base
 // cell), cubes of kCube[0] x kCube[1] x kCube[2] cells.
 constexpr int kCubeShift[3] = {4, 3, 3};
@@ -108,6 +112,7 @@ struct SimDev {
   int32_t nnodes;
   int32_t nmeshes;
   int32_t maxn;           // SoA stride of the node arrays (capacity)
+  int32_t skin;           // candidate-list skin in cells (0: lists rebuilt every step)
   // state
   IBL_G(void) f[2];             // populations, [19][ncell] in storage format
   IBL_G(void) u;                // [3][ncell] velocity (compute precision)
@@ -118,9 +123,12 @@ struct SimDev {
   IBL_G(double) U;              // [3][max_nodes] interpolated velocities
   IBL_G(void) rec;              // [max_nodes] NodeRec
   IBL_G(double) escr;           // [3 * max_nodes][9] per-edge force shares (G0, G3, F1)
-  IBL_G(int32_t) bcount;        // [nbrick]
-  IBL_G(uint32_t) bmax;         // [nbrick] largest |F component| among the brick's candidates (float bits)
-  IBL_G(int32_t) blist;         // [nbrick][kCandCap]
+  IBL_G(int32_t) bcount;        // [2][nbrick] candidate counts of the two list buffers
+  IBL_G(int32_t) blist;         // [2][nbrick][kCandCap]
+  IBL_G(int16_t) bb0;           // [max_nodes][4] stencil base cell when the lists were built
+  IBL_G(uint32_t) fmax;         // [2] largest |F component| of the step, by step parity (float bits)
+  IBL_G(int32_t) lctl;          // [4] list buffer in use after the step of parity 0, 1;
+                                //     lists rebuilt by the step of parity 0, 1 (flags)
   IBL_G(int32_t) hcount;        // [ncube] nodes per home cube
   IBL_G(int32_t) hlist;         // [ncube][kHomeCap]
   // meshes
@@ -185,6 +193,7 @@ hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int ini
                        hipStream_t s);
 hipError_t launch_template_rest(const SimDev* sim, int tmpl, int nedges, const double* xref,
                                 hipStream_t s);
+hipError_t launch_reset_lists(const SimDev* sim, int64_t nbrick, hipStream_t s);
 hipError_t launch_phase(int storage, const SimDev* sims, const Items& it, int phase, int mode,
                         hipStream_t s);
 // `steps` timesteps (mode 0) followed by one counter advance, or one

@@ -164,11 +164,12 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     for (int64_t j = b * kBrickThreads + tid; j < S.ncube; j += S.nbrick * kBrickThreads) S.hcount[j] = 0;
     if (tid == 0) {
       S.bcount[b] = 0;
-      S.bmax[b] = 0u;
+      S.bcount[S.nbrick + b] = 0;
       if (b == 0) {
         *S.step = 0;
         *S.remaining = 0;
         *S.health = 0u;
+        reset_list_control(S);
       }
     }
     int ox, oy, oz;
@@ -177,6 +178,18 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     if (x >= S.n[0] || y >= S.n[1]) continue;
     for (int k = 0; k < kBrickZ && oz + k < S.n[2]; ++k) init_cell<ST>(S, x, y, oz + k, profile);
   }
+}
+
+// Candidate lists emptied and marked for a rebuild at the next step (after
+// the nodes or the step counter were set from the host).
+__global__ void k_reset_lists(const SimDev* __restrict__ sim) {
+  const SimDev& S = *sim;
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < S.nbrick) {
+    S.bcount[b] = 0;
+    S.bcount[S.nbrick + b] = 0;
+  }
+  if (b == 0) reset_list_control(S);
 }
 
 // ----------------------------------------------------------- rest state --
@@ -283,16 +296,26 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
     brick_origin(S, b, ox, oy, oz);
     const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
     const int bx = S.bs[0], by = S.bs[1], bz = S.bs[2];
-    // ---- force spreading, Eq. (15): the brick's candidates, one per lane
-    int cnt = S.has_ib ? S.bcount[b] : 0;
+    const int64_t stepn = *S.step + it.sub;
+    const int par = (int)(stepn & 1);
+    // ---- force spreading, Eq. (15): the brick's candidates, one per lane.
+    // List buffer: the one in use after the previous step, or the other one
+    // when this step rebuilt the lists (every step without a skin; an
+    // observation always builds into the free buffer).
+    const int rb = mode == 1 || S.skin == 0 ? 1 : S.lctl[2 + par];
+    const int buf = S.lctl[par ^ 1] ^ rb;
+    const int64_t bl = buf * S.nbrick + b;
+    int cnt = S.has_ib ? S.bcount[bl] : 0;
     const bool ib = cnt > 0;  // uniform
     R inv = (R)0;
     if (ib) {
-      const uint32_t fmx = S.bmax[b];
+      // one fixed-point scale per simulation and step: the sums do not depend
+      // on which nodes share a brick
+      const uint32_t fmx = S.fmax[par];
       if (tid == 0 && cnt > kCandCap) atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
       cnt = cnt > kCandCap ? kCandCap : cnt;
       const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
-      const GLB int32_t* list = S.blist + b * kCandCap;
+      const GLB int32_t* list = S.blist + bl * kCandCap;
       // this lane's first candidate, fetched before the field is cleared
       NodeRec<R> q;
       if (tid < cnt) q = *(const NodeRec<R>*)(rec + list[tid]);
@@ -308,11 +331,13 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       sh = sh > 120 ? 120 : sh;  // forces below ~1e-28: their shares round to zero
       const R sc = (R)ldexp(1.0, sh);
       inv = (R)ldexp(1.0, -sh);
-      for (int i = tid; i < cnt; i += blockDim.x) {
+      for (int i = tid; i < cnt; i += kBrickThreads) {
         if (i != tid) q = *(const NodeRec<R>*)(rec + list[i]);
-        // a node is interpolated through its home cube's list (one entry per node)
+        // a node is interpolated through its home cube's list (one entry per
+        // node); a node that is no longer valid is neither spread nor moved
+        const bool val = q.valid != 0;
         uint16_t hrank = 0xffffu;
-        if ((unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
+        if (val && (unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
             (unsigned)(q.base[2] - oz) < (unsigned)bz) {
           const int lc = (q.base[0] >> kCubeShift[0]) - (ox >> kCubeShift[0]) +
                          nlx * ((q.base[1] >> kCubeShift[1]) - (oy >> kCubeShift[1]));
@@ -323,6 +348,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         axis_cells(q.base[0], ox, nx, S.wall[0], bx, lx, mx);
         axis_cells(q.base[1], oy, ny, S.wall[1], by, ly, my);
         axis_cells(q.base[2], oz, nz, S.wall[2], bz, lz, mz);
+        if (!val) mz = 0;
         const R fx = q.F[0] * sc, fy = q.F[1] * sc, fz = q.F[2] * sc;
         R w3[3][4];
         rec_weights(q, S.delta, w3);
@@ -357,17 +383,21 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         const int cube = cube0 + lc % nlx + S.nq[0] * (lc / nlx);
         if (pos < kHomeCap) S.hlist[(int64_t)cube * kHomeCap + pos] = list[i];
       }
-      if (tid == 0) {  // every lane has read the list: the next step rebuilds it
-        S.bcount[b] = 0;
-        S.bmax[b] = 0u;
+    }
+    if (S.has_ib && tid == 0) {
+      // an observation's lists are dropped once read; after a rebuild the
+      // retired buffer becomes the (empty) free one
+      if (mode == 1) S.bcount[bl] = 0;
+      else if (rb) S.bcount[(buf ^ 1) * S.nbrick + b] = 0;
+      if (b == 0) {
+        if (mode == 0) S.lctl[par] = buf;
+        S.fmax[par ^ 1] = 0u;  // the next step's maximum starts from zero
       }
     }
     // ---- collide-stream, a column of kBrickZ cells per thread
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
     if (x < nx && y < ny) {
       const int64_t nc = S.ncell;
-      const int64_t stepn = *S.step + it.sub;
-      const int par = (int)(stepn & 1);
       const uint32_t salt = (uint32_t)stepn * 0x85EBCA77u + 0x165667B1u;
       const GLB T* src = (const GLB T*)S.f[par];
       GLB T* dst = (GLB T*)S.f[par ^ 1];
@@ -550,6 +580,11 @@ hipError_t launch_init(int storage, const SimDev* sims, const Items& it, int pro
   if (storage == kF64) hipLaunchKernelGGL(k_init<kF64>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
   else if (storage == kF32) hipLaunchKernelGGL(k_init<kF32>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
   else hipLaunchKernelGGL(k_init<kF16>, dim3(grid), dim3(kBrickThreads), 0, s, sims, it, profile);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_lists(const SimDev* sim, int64_t nbrick, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_lists, dim3((unsigned)((nbrick + 255) / 256)), dim3(256), 0, s, sim);
   return hipGetLastError();
 }
 

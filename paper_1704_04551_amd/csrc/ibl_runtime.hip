@@ -76,7 +76,7 @@ size_t rec_bytes(int st) { return st == kF64 ? sizeof(NodeRec<double>) : sizeof(
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
-  size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, bmax, blist, hcount, hlist;
+  size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, blist, bb0, fmax, lctl, hcount, hlist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
   size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0, txref;
   size_t step, remaining, health, red, red_out, simdev, items;
@@ -95,6 +95,7 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   if (d->storage < 0 || d->storage > 2) return fail(IBL_ERR_ARG, "unknown storage");
   if (d->brick_x != 0 && d->brick_x != 16 && d->brick_x != 32 && d->brick_x != 64)
     return fail(IBL_ERR_ARG, "brick_x must be 0, 16, 32 or 64");
+  if (d->skin != 0 && d->skin != 1) return fail(IBL_ERR_ARG, "skin must be 0 or 1");
   if (d->delta < 0 || d->delta > 1) return fail(IBL_ERR_ARG, "unknown delta kernel");
   if (d->init_profile < 0 || d->init_profile > 1) return fail(IBL_ERR_ARG, "unknown init profile");
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||
@@ -144,9 +145,11 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.U = take(3 * maxn * 8);
   L.rec = take(maxn * rec_bytes(st));
   L.escr = take(maxn * 3 * 9 * 8);
-  L.bcount = take((size_t)nb * 4);
-  L.bmax = take((size_t)nb * 4);
-  L.blist = take(ib ? (size_t)nb * kCandCap * 4 : 4);
+  L.bcount = take(2 * (size_t)nb * 4);
+  L.blist = take(ib ? 2 * (size_t)nb * kCandCap * 4 : 4);
+  L.bb0 = take(maxn * 8);
+  L.fmax = take(2 * 4);
+  L.lctl = take(4 * 4);
   L.hcount = take((size_t)nq * 4);
   L.hlist = take(ib ? (size_t)nq * kHomeCap * 4 : 4);
   L.mesh_tmpl = take((size_t)d->max_meshes * 4);
@@ -384,6 +387,7 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.delta = desc->delta;
   d.tau = desc->tau;
   d.maxn = desc->max_nodes;
+  d.skin = desc->skin;
   d.f[0] = A + L.f0;
   d.f[1] = A + L.f1;
   d.u = A + L.u;
@@ -395,8 +399,10 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.rec = A + L.rec;
   d.escr = (double*)(A + L.escr);
   d.bcount = (int32_t*)(A + L.bcount);
-  d.bmax = (uint32_t*)(A + L.bmax);
   d.blist = (int32_t*)(A + L.blist);
+  d.bb0 = (int16_t*)(A + L.bb0);
+  d.fmax = (uint32_t*)(A + L.fmax);
+  d.lctl = (int32_t*)(A + L.lctl);
   d.hcount = (int32_t*)(A + L.hcount);
   d.hlist = (int32_t*)(A + L.hlist);
   d.ncube = L.ncube;
@@ -589,6 +595,7 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
   HIPCHK(hipMemcpyAsync(d.mesh_off + S->nmesh, &off, 4, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_ks + S->nmesh, &ks, 8, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_kb + S->nmesh, &kb, 8, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // new nodes: rebuild at the next step
   HIPCHK(hipStreamSynchronize(S->stream));
   S->mesh_tmpl.push_back(tmpl);
   S->mesh_off.push_back(off);
@@ -769,6 +776,8 @@ ibl_status ibl_write_state(ibl_sim S, const void* buf, size_t bytes) {
     p += 8 * (size_t)S->nnodes;
   }
   HIPCHK(hipMemcpy(S->hd.step, &h.step, 8, hipMemcpyHostToDevice));
+  HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // positions replaced: rebuild
+  HIPCHK(hipStreamSynchronize(S->stream));
   return IBL_OK;
 }
 

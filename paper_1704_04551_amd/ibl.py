@@ -47,6 +47,7 @@ class SimDesc(ctypes.Structure):
         ("max_template_nodes", ctypes.c_int32),
         ("max_template_edges", ctypes.c_int32),
         ("brick_x", ctypes.c_int32),
+        ("skin", ctypes.c_int32),
     ]
 
 
@@ -106,7 +107,7 @@ def _p(a):
 
 def make_desc(n, tau, g_body=(0, 0, 0), wall=(0, 0, 0), u_lo=None, u_hi=None, storage="f32",
               delta="cos", init_profile=0, max_nodes=0, max_meshes=0, max_templates=0,
-              max_template_nodes=0, max_template_edges=0, brick_x=0) -> SimDesc:
+              max_template_nodes=0, max_template_edges=0, brick_x=0, skin=0) -> SimDesc:
     d = SimDesc()
     for a in range(3):
         d.n[a] = int(n[a])
@@ -128,6 +129,7 @@ def make_desc(n, tau, g_body=(0, 0, 0), wall=(0, 0, 0), u_lo=None, u_hi=None, st
     d.max_template_nodes = int(max_template_nodes)
     d.max_template_edges = int(max_template_edges)
     d.brick_x = int(brick_x)
+    d.skin = int(skin)
     return d
 
 
@@ -258,7 +260,7 @@ class Sim:
 
     # -- from a workload spec ----------------------------------------------
     @classmethod
-    def from_spec(cls, spec, storage="f32", device=None, arena=None, brick_x=0):
+    def from_spec(cls, spec, storage="f32", device=None, arena=None, brick_x=0, skin=0):
         """Build from a ``workloads.SimSpec``; capsules sharing a non-empty
         shape key share one template (rest state of the first of them)."""
         groups = template_groups(spec)
@@ -268,7 +270,7 @@ class Sim:
         desc = make_desc(spec.n, spec.tau, spec.g_body, spec.wall, spec.u_lo, spec.u_hi, storage,
                          spec.delta, spec.init_profile, max_nodes=nodes,
                          max_meshes=len(spec.capsules), max_templates=len(groups),
-                         max_template_nodes=tn, max_template_edges=te, brick_x=brick_x)
+                         max_template_nodes=tn, max_template_edges=te, brick_x=brick_x, skin=skin)
         sim = cls(desc, device=device, arena=arena)
         mesh_of = {}
         for grp in groups:

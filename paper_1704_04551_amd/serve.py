@@ -61,13 +61,16 @@ class Job:
 
 
 class GpuBackend:
-    """Resident simulations through the C-ABI (libibl.so)."""
+    """Resident simulations through the C-ABI (libibl.so).  `skin` is the
+    candidate-list skin of every job (1 by default: served jobs are small
+    suspensions, where keeping the lists between rebuilds pays)."""
 
-    def __init__(self, storage="f32", device="cuda:0"):
+    def __init__(self, storage="f32", device="cuda:0", skin=1):
         from . import ibl
         self.ibl = ibl
         self.storage = storage
         self.device = device
+        self.skin = int(skin)
         self._batch = None
         self._members = ()     # the batch's simulations (they must outlive it)
 
@@ -79,11 +82,11 @@ class GpuBackend:
         desc = ibl.make_desc(spec.n, spec.tau, spec.g_body, spec.wall, spec.u_lo, spec.u_hi,
                              self.storage, spec.delta, spec.init_profile, max_nodes=spec.nodes,
                              max_meshes=len(spec.capsules), max_templates=len(groups),
-                             max_template_nodes=tn, max_template_edges=te)
+                             max_template_nodes=tn, max_template_edges=te, skin=self.skin)
         return ibl.sim_bytes(desc)
 
     def create(self, spec):
-        return self.ibl.Sim.from_spec(spec, storage=self.storage, device=self.device)
+        return self.ibl.Sim.from_spec(spec, storage=self.storage, device=self.device, skin=self.skin)
 
     def step(self, sims, steps):
         if self._batch is None or len(sims) != len(self._members) or any(

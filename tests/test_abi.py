@@ -63,7 +63,8 @@ def test_sim_bytes_scales_with_storage():
 
 @pytest.mark.parametrize("kw", [dict(tau=0.5), dict(tau=0.3), dict(n=(3, 32, 32)), dict(storage=7),
                                 dict(delta=5), dict(init_profile=3), dict(max_nodes=-1),
-                                dict(brick_x=8), dict(brick_x=128), dict(n=(32768, 4, 4)),
+                                dict(brick_x=8), dict(brick_x=128), dict(skin=2), dict(skin=-1),
+                                dict(n=(32768, 4, 4)),
                                 dict(n=(1024, 1024, 1024), storage="f32")])
 def test_invalid_descriptor_rejected(kw):
     with pytest.raises(ibl.IBLError) as e:

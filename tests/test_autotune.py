@@ -1,5 +1,5 @@
-"""Brick-width autotuner: selection logic on fake timings (no GPU), and on
-the GPU every width runs the same physics within the fixed-point resolution."""
+"""Brick-shape and list-skin autotuner: selection logic on fake timings (no
+GPU), and on the GPU every (width, skin) pair runs bitwise the same physics."""
 import numpy as np
 import pytest
 
@@ -20,49 +20,58 @@ def test_default_width_follows_x_extent():
     assert autotune.default_width(20) == 16
 
 
-def test_picks_fastest_width():
-    times = {64: 1.30, 32: 1.00, 16: 1.20}
-    best, t = autotune.tune_brick_x(Spec((96, 64, 64)), runner=lambda w: times[w], use_memo=False)
-    assert best == 32 and t == times
+def test_picks_fastest_pair():
+    times = {(64, 0): 1.30, (32, 0): 1.10, (16, 0): 1.20, (64, 1): 1.25, (32, 1): 1.00, (16, 1): 1.40}
+    best, t = autotune.tune(Spec((96, 64, 64)), runner=lambda w, k: times[(w, k)], use_memo=False)
+    assert best == (32, 1) and t == times
 
 
 def test_ties_resolve_toward_default():
-    times = {64: 1.005, 32: 1.00, 16: 1.30}
-    best, _ = autotune.tune_brick_x(Spec((128, 64, 64)), runner=lambda w: times[w], use_memo=False)
-    assert best == 64  # within 2 % of the fastest: the built-in choice stays
+    times = {(64, 0): 1.005, (32, 0): 1.00, (16, 0): 1.30, (64, 1): 1.001, (32, 1): 1.3, (16, 1): 1.3}
+    best, _ = autotune.tune(Spec((128, 64, 64)), runner=lambda w, k: times[(w, k)], use_memo=False)
+    assert best == (64, 0)  # within 2 % of the fastest: the built-in choice stays
+
+
+def test_ties_prefer_no_skin_then_wider():
+    assert autotune.pick({(32, 1): 1.0, (16, 0): 1.01, (32, 0): 1.015}, nx=128) == (32, 0)
+    assert autotune.pick({(32, 1): 1.0, (16, 1): 1.0}, nx=128) == (32, 1)
 
 
 def test_memo_skips_retiming():
     calls = []
     spec = Spec((40, 40, 40))
     autotune._memo.clear()
-    b1, _ = autotune.tune_brick_x(spec, runner=lambda w: calls.append(w) or float(w))
-    b2, t2 = autotune.tune_brick_x(spec, runner=lambda w: calls.append(w) or float(w))
-    assert b1 == b2 == 16 and len(calls) == 3 and t2 == {}
+    b1, _ = autotune.tune(spec, runner=lambda w, k: calls.append((w, k)) or float(w + 100 * k))
+    b2, t2 = autotune.tune(spec, runner=lambda w, k: calls.append((w, k)) or float(w + 100 * k))
+    assert b1 == b2 == (16, 0) and len(calls) == 6 and t2 == {}
 
 
 @pytest.mark.gpu
-def test_every_width_matches_default_within_resolution():
-    """The brick shape changes only which nodes share a fixed-point scale:
-    fields and node positions agree across widths to ~1e-6 of their range."""
+def test_every_shape_is_bitwise_identical():
+    """Brick width and list skin change only how the work is split: the
+    spreading sums are exact fixed-point sums with one scale per simulation,
+    so fields and node positions are bitwise identical for every pair, also
+    across the steps where skin lists are rebuilt."""
     from paper_1704_04551_amd import ibl
     spec = W.config_small(delta="cos", n=32)
     out = {}
     for bx in (16, 32, 64):
-        s = ibl.Sim.from_spec(spec, storage="f32", brick_x=bx)
-        s.step(60)
-        s.sync()
-        out[bx] = (s.fields(rho=False, g=False)[1], s.nodes(0)[0])
-        s.close()
-    u0, x0 = out[32]
-    for bx in (16, 64):
-        u, x = out[bx]
-        assert np.abs(u - u0).max() < 1e-5 * np.abs(u0).max()
-        assert np.abs(x - x0).max() < 1e-6
+        for skin in (0, 1):
+            s = ibl.Sim.from_spec(spec, storage="f32", brick_x=bx, skin=skin)
+            s.step(700)
+            s.sync()
+            out[(bx, skin)] = (s.fields(rho=False, g=False)[1], s.nodes(0)[0])
+            s.close()
+    u0, x0 = out[(32, 0)]
+    # nodes moved well past the one-cell skin: the skin lists were rebuilt
+    assert np.abs(x0 - spec.capsules[0].x).max() > 1.5
+    for key, (u, x) in out.items():
+        assert np.array_equal(u, u0), key
+        assert np.array_equal(x, x0), key
 
 
 @pytest.mark.gpu
 def test_tuner_runs_on_gpu():
     spec = W.config_small(delta="cos", n=32)
-    best, t = autotune.tune_brick_x(spec, steps=10, warmup=2, use_memo=False)
-    assert best in (16, 32, 64) and set(t) == {16, 32, 64} and all(v > 0 for v in t.values())
+    best, t = autotune.tune(spec, steps=10, warmup=2, use_memo=False)
+    assert best in t and len(t) == 6 and all(v > 0 for v in t.values())
