@@ -138,15 +138,17 @@ __device__ void append_skin(const SimDev& S, int buf, const int base[3], int gid
 
 // List state of a simulation's current step, read by the force kernels:
 // rebuild flag (always without a skin; an observation always builds its own
-// lists, into the free buffer) and the buffer this step's lists are in.
+// lists, into the free buffer) and the buffer this step's lists are in (the
+// first one without a skin, emptied by the spreading once read).
 struct ListStep {
   int par, rb, buf;
 };
 __device__ __forceinline__ ListStep list_step(const SimDev& S, const Items& it, int mode) {
   ListStep L;
+  const int4 lc4 = *(const GLB int4*)S.lctl;  // loaded with the step, selected after
   L.par = (int)((*S.step + it.sub) & 1);
-  L.rb = mode == 1 || S.skin == 0 ? 1 : S.lctl[2 + L.par];
-  L.buf = S.lctl[L.par ^ 1] ^ L.rb;
+  L.rb = mode == 1 || S.skin == 0 ? 1 : (L.par ? lc4.w : lc4.z);
+  L.buf = S.skin == 0 ? 0 : (L.par ? lc4.x : lc4.y) ^ L.rb;
   return L;
 }
 
@@ -742,7 +744,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
     const int s = find_sim(it.cube_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
-    const int next_par = (int)((*S.step + it.sub + 1) & 1);
+    const int next_par = S.skin ? (int)((*S.step + it.sub + 1) & 1) : 0;
     const int64_t h = item - it.cube_off[s];
     int cnt = S.hcount[h];
     if (cnt == 0) continue;  // no node has its base here (uniform)

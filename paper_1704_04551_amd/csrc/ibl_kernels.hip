@@ -299,11 +299,16 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
     const int64_t stepn = *S.step + it.sub;
     const int par = (int)(stepn & 1);
     // ---- force spreading, Eq. (15): the brick's candidates, one per lane.
-    // List buffer: the one in use after the previous step, or the other one
-    // when this step rebuilt the lists (every step without a skin; an
-    // observation always builds into the free buffer).
-    const int rb = mode == 1 || S.skin == 0 ? 1 : S.lctl[2 + par];
-    const int buf = S.lctl[par ^ 1] ^ rb;
+    // List buffer: without a skin always the first, rebuilt every step and
+    // emptied once read.  With a skin: the one in use after the previous
+    // step, or the other one when this step rebuilt the lists (an observation
+    // always builds into the free buffer).
+    int rb = 1, buf = 0;
+    if (S.skin) {  // uniform
+      const int4 lc4 = *(const GLB int4*)S.lctl;
+      rb = mode == 1 ? 1 : (par ? lc4.w : lc4.z);
+      buf = (par ? lc4.x : lc4.y) ^ rb;
+    }
     const int64_t bl = buf * S.nbrick + b;
     int cnt = S.has_ib ? S.bcount[bl] : 0;
     const bool ib = cnt > 0;  // uniform
@@ -385,9 +390,9 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       }
     }
     if (S.has_ib && tid == 0) {
-      // an observation's lists are dropped once read; after a rebuild the
-      // retired buffer becomes the (empty) free one
-      if (mode == 1) S.bcount[bl] = 0;
+      // lists rebuilt every step and an observation's lists are dropped once
+      // read; after a rebuild the retired buffer becomes the (empty) free one
+      if (mode == 1 || S.skin == 0) S.bcount[bl] = 0;
       else if (rb) S.bcount[(buf ^ 1) * S.nbrick + b] = 0;
       if (b == 0) {
         if (mode == 0) S.lctl[par] = buf;

@@ -145,9 +145,11 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.U = take(3 * maxn * 8);
   L.rec = take(maxn * rec_bytes(st));
   L.escr = take(maxn * 3 * 9 * 8);
+  // the second list buffer and the build-time base cells only with a skin
+  const size_t nbuf = d->skin ? 2 : 1;
   L.bcount = take(2 * (size_t)nb * 4);
-  L.blist = take(ib ? 2 * (size_t)nb * kCandCap * 4 : 4);
-  L.bb0 = take(maxn * 8);
+  L.blist = take(ib ? nbuf * nb * kCandCap * 4 : 4);
+  L.bb0 = take(d->skin ? maxn * 8 : 8);
   L.fmax = take(2 * 4);
   L.lctl = take(4 * 4);
   L.hcount = take((size_t)nq * 4);
