@@ -192,9 +192,11 @@ def test_bitwise_repeatable():
         assert np.array_equal(a.nodes(m)[0], b.nodes(m)[0])
 
 
-def test_batch_equals_alone():
+@pytest.mark.parametrize("skins", [(0, 0, 0), (1, 0, 1)])
+def test_batch_equals_alone(skins):
     """Uneven batch (three sims, different shapes and step counts) advanced in
-    one launch per phase: bitwise the results of each sim run alone."""
+    one launch per phase: bitwise the results of each sim run alone, also when
+    the members use different list skins (alone: no skin)."""
     specs = [_ragged_spec(), W.config_small(delta="cos", n=24)]
     specs.append(W.SimSpec(n=(16, 12, 20), tau=0.6, g_body=(1e-5, 0, 0), wall=(0, 1, 1)))
     steps = [23, 41, 17]
@@ -204,7 +206,7 @@ def test_batch_equals_alone():
         s.step(k)
         s.sync()
         alone.append(s)
-    batch_sims = [ibl.Sim.from_spec(sp, storage="f32") for sp in specs]
+    batch_sims = [ibl.Sim.from_spec(sp, storage="f32", skin=k) for sp, k in zip(specs, skins)]
     B = ibl.Batch(batch_sims)
     B.step(steps)
     for s in batch_sims:
@@ -237,16 +239,19 @@ def test_dirty_arena_gives_identical_results():
             assert np.array_equal(a, b)
 
 
-def test_checkpoint_roundtrip_bitwise():
+@pytest.mark.parametrize("skin", [0, 1])
+def test_checkpoint_roundtrip_bitwise(skin):
+    """Restoring a state rebuilds the candidate lists: the continued run is
+    bitwise the uninterrupted one (reference without a skin)."""
     spec = _ragged_spec()
     ref = ibl.Sim.from_spec(spec, storage="f32")
     ref.step(20)
     ref.sync()
-    a = ibl.Sim.from_spec(spec, storage="f32")
+    a = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
     a.step(10)
     a.sync()
     blob = a.read_state()
-    b = ibl.Sim.from_spec(spec, storage="f32")
+    b = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
     b.write_state(blob)
     assert b.step_count == 10
     b.step(10)
@@ -254,6 +259,24 @@ def test_checkpoint_roundtrip_bitwise():
     assert np.array_equal(ref.fields()[1], b.fields()[1])
     for m in range(3):
         assert np.array_equal(ref.nodes(m)[0], b.nodes(m)[0])
+
+
+@pytest.mark.parametrize("skin", [0, 1])
+def test_observation_does_not_perturb(skin):
+    """Reading observables mid-run (which builds its own candidate lists) leaves
+    the run bitwise unchanged, across skin-list rebuilds."""
+    spec = W.config_small(delta="cos", n=32)
+    ref = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
+    ref.step(500)
+    ref.sync()
+    s = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
+    for _ in range(5):
+        s.step(100)
+        s.fields()
+        s.nodes(0)
+    assert np.abs(ref.nodes(0)[0] - spec.capsules[0].x).max() > 1.0  # past the skin
+    assert np.array_equal(ref.fields()[1], s.fields()[1])
+    assert np.array_equal(ref.nodes(0)[0], s.nodes(0)[0])
 
 
 def test_conservation_and_health():
