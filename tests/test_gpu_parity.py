@@ -323,3 +323,35 @@ def test_health_flags_bad_state():
     s2.step(2)
     m, p, h = s2.conservation()
     assert h & 0x1
+
+
+def test_rbc_channel_full_size_vs_oracle():
+    """The headline workload at full size (256x128x128 channel, 1018 Evans-Fung
+    cells, 653,556 nodes) in the bench's launch configuration (FP32, 64-wide
+    bricks, no skin).  After two steps: u and X against the FP64 oracle within
+    the FP32 bar; the one-cell-skin run bitwise equal; every capsule's
+    fixed-point membrane forces summing to exactly zero."""
+    spec = W.config_rbc_channel()
+    assert len(spec.capsules) == 1018 and spec.nodes == 653556
+    o = oracle_from_spec(spec)
+    o.step(2)
+    _, uo, _ = o.observe()
+    res = {}
+    for skin in (0, 1):
+        g = ibl.Sim.from_spec(spec, storage="f32", brick_x=64, skin=skin)
+        g.step(2)
+        g.sync()
+        _, ug, _ = g.fields(rho=False, g=False)
+        nodes = [g.nodes(m) for m in range(len(spec.capsules))]
+        g.close()
+        res[skin] = (ug, nodes)
+    ug, nodes = res[0]
+    umax, _ = field_err(ug, uo, fluid_mask(spec))
+    assert umax < 1e-5, umax
+    xr = max(node_err(nodes[m][0], o.nodes(m)[0], c.x)[1] for m, c in enumerate(spec.capsules))
+    assert xr < 1e-5, xr
+    assert np.array_equal(res[1][0], ug)
+    for (xa, _, fa), (xb, _, fb) in zip(res[1][1], nodes):
+        assert np.array_equal(xa, xb) and np.array_equal(fa, fb)
+    for _, _, f in nodes:
+        assert not np.any(f.sum(axis=0))  # exact: multiples of 2^-50 far below 2^53 ulps
