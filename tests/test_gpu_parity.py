@@ -323,6 +323,19 @@ def test_health_flags_bad_state():
     s2.step(2)
     m, p, h = s2.conservation()
     assert h & 0x1
+    # a membrane force share beyond one lattice unit (FP32/FP16 storage sum
+    # forces in fixed point): a stiff capsule stretched by 40 %
+    sp3 = W.config_small(delta="cos", n=32)
+    c = sp3.capsules[0]
+    ctr = c.x.mean(axis=0)
+    c.x = ctr + 1.4 * (c.x - ctr)
+    c.ks = 50.0
+    s3 = ibl.Sim.from_spec(sp3, storage="f32")
+    s3.step(1)
+    with pytest.raises(ibl.IBLError) as e:
+        s3.sync()
+    assert e.value.status == -5
+    assert s3.conservation()[2] & 0x40
 
 
 def test_rbc_channel_full_size_vs_oracle():
