@@ -22,9 +22,10 @@ Prints one JSON line.
   state is compared with it (``error_vs_oracle``).
 * ``batched``: 64 uneven simulations in one batched launch sequence against
   the same simulations run one after another.
-* ``served``: a Poisson stream of Jeffery-orbit jobs through the serving loop
-  (continuous batching) and, on the same stream, one job at a time (the
-  plain form): p50/p99 latency and aggregate MLUPS of each.
+* ``served``: Poisson streams of Jeffery-orbit jobs through the serving loop
+  (continuous batching): full-length jobs at the stated rate (rejections,
+  capacity) and at a sustainable rate (p50/p99 latency), and shortened jobs
+  batched against one job at a time (the plain form).
 * ``autotune``: the lattice brick width (16 / 32 / 64 cells) and the
   candidate-list skin (0 / 1 cell) are timed on the workload first
   (``--no-autotune``, or ``--brick-x`` with ``--skin``, to skip).
@@ -168,33 +169,56 @@ def run_batched(storage, steps, skin):
             "batched_s": round(tb, 4), "plain_s": round(tp, 4), "bitwise_same": bool(same)}, xs
 
 
+def _serve(storage, jobs, pool, slots, queue_cap, time_limit):
+    from paper_1704_04551_amd.serve import GpuBackend, Job, Server
+    srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=slots, queue_cap=queue_cap)
+    try:
+        st = srv.run([Job(j.jid, j.spec, j.arrival, j.steps) for j in jobs], time_limit=time_limit)
+    finally:
+        srv.close()
+    return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+
+
 def run_served(storage, seconds, rate, step_scale, seed=1005):
     """Poisson arrivals of Jeffery-orbit jobs (ellipsoid of 642 nodes, ks
-    0.05, AR 1.5-4, cubic lattice 48-128, shear rate 0.005) through the
-    serving loop.  Job lengths are the workload's 2000-20000 steps scaled by
-    `step_scale`, so the stream fits the window."""
+    0.05, AR 1.5-4, cubic lattice 48-128, shear rate 0.005, 2000-20000 steps)
+    through the serving loop, `seconds` of arrivals per run:
+
+    * stated: `rate` jobs/s of full-length jobs with a bounded queue (64).
+      That is several times more work than one GPU does, so jobs are rejected
+      and the rest queue; the run stops at 3 x `seconds`.  Its MLUPS is the
+      server's capacity.
+    * sustainable: full-length jobs at 0.7 x that capacity / the mean work
+      per job, run to completion: the meaningful tail latency.
+    * scaled: job lengths x `step_scale` at `rate`: continuous batching
+      against the plain form (one job at a time, first come first served) on
+      the same arrival stream.
+    """
     import torch
     from paper_1704_04551_amd import workloads as W
-    from paper_1704_04551_amd.serve import GpuBackend, Job, Server, poisson_jobs
-    lo, hi = max(1, int(2000 * step_scale)), max(1, int(20000 * step_scale))
-    jobs = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, steps=(lo, hi)), seed)
+    from paper_1704_04551_amd.serve import poisson_jobs
     free, total = torch.cuda.mem_get_info()
     pool = int(0.5 * free)
-    out = {}
-    # continuous batching, then the plain form (one job at a time, first come
-    # first served) on the same arrival stream
+    edges = (48, 64, 80, 96, 112, 128)  # the job generator's lattice edges (uniform)
+    mean_work = float(np.mean([e ** 3 for e in edges])) * (2000 + 20000) / 2.0
+    out = {"window_s": seconds, "pool_bytes": pool}
+    full = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, edges=edges), seed)
+    out["stated"] = dict(_serve(storage, full, pool, 64, 64, 3 * seconds), rate_jobs_s=rate, jobs=len(full))
+    _log("served (stated rate): %s" % out["stated"])
+    cap = out["stated"]["mlups"] * 1e6
+    rate_s = 0.7 * cap / mean_work
+    sus = poisson_jobs(rate_s, seconds, lambda rng: W.job_served(rng, edges=edges), seed + 1)
+    out["sustainable"] = dict(_serve(storage, sus, pool, 64, 4096, 10 * seconds),
+                              rate_jobs_s=round(rate_s, 3), jobs=len(sus))
+    _log("served (sustainable rate): %s" % out["sustainable"])
+    lo, hi = max(1, int(2000 * step_scale)), max(1, int(20000 * step_scale))
+    short = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, edges=edges, steps=(lo, hi)), seed)
+    out["scaled"] = {"rate_jobs_s": rate, "jobs": len(short), "job_steps": [lo, hi]}
     for name, slots in (("batched", 64), ("plain", 1)):
-        stream = [Job(j.jid, j.spec, j.arrival, j.steps) for j in jobs]
-        srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=slots, queue_cap=4096)
-        try:
-            st = srv.run(stream, time_limit=3 * seconds)
-        finally:
-            srv.close()
-        out[name] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
-        _log("served (%s): %s" % (name, out[name]))
-    out.update({"rate_jobs_s": rate, "window_s": seconds, "jobs": len(jobs), "job_steps": [lo, hi],
-                "pool_bytes": pool, "p50_s": out["batched"]["p50_s"], "p99_s": out["batched"]["p99_s"],
-                "mlups": out["batched"]["mlups"]})
+        out["scaled"][name] = _serve(storage, short, pool, slots, 4096, 3 * seconds)
+        _log("served (scaled jobs, %s): %s" % (name, out["scaled"][name]))
+    out.update({"p50_s": out["sustainable"]["p50_s"], "p99_s": out["sustainable"]["p99_s"],
+                "capacity_mlups": out["stated"]["mlups"]})
     return out
 
 

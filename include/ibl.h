@@ -78,7 +78,7 @@ typedef enum {
 #define IBL_HEALTH_OVERFLOW 0x10u    /* a brick's candidate list overflowed */
 #define IBL_HEALTH_NONFINITE_X 0x20u /* a node position is NaN or Inf */
 #define IBL_HEALTH_FORCE_RANGE 0x40u /* a membrane force share was NaN or beyond
-                                        1 lattice unit (FP32 / FP16 storage
+                                        2048 lattice units (FP32 / FP16 storage
                                         accumulate forces in fixed point) */
 
 typedef struct {

@@ -463,25 +463,30 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
 // 2^-kFxBits.  Integer addition is associative, so a node's sum does not
 // depend on the order in which its edges land, and the fourth share of an
 // edge is formed in integers as minus the other three, so the membrane's
-// internal forces sum to exactly zero.  A share component is limited to
-// kFxLimit = 1 lattice unit in magnitude (flagged in the health word beyond
-// it: a force that large is far past any stable lattice-Boltzmann state); a
-// node meets at most 16 shares on these templates, so a sum stays below
-// 2^(63-kFxBits).  With |v 2^50| < 2^51 the rounding to an integer is one FMA:
-// v 2^50 + 1.5 2^52 rounds to an integer of the binade [2^52, 2^53), whose
-// bit pattern minus that of 1.5 2^52 is round(v 2^50).
+// internal forces sum to exactly zero.
+//
+// Resolution 2^-40 (9.1e-13 lattice units, far below the float precision of
+// the spreading record).  Single shares are much larger than node sums where
+// a triangle is nearly degenerate (the bending share grows as 1 / its area,
+// and the shares cancel at the node), so the range is wide: a share component
+// is limited to kFxLimit = 2048 lattice units (flagged in the health word
+// beyond it); a node meets at most 16 shares on these templates, the fourth of
+// an edge at most three times the limit, so a sum stays below 2^17 << 2^23 =
+// 2^(63-kFxBits).  With |v 2^40| < 2^51 the rounding to an integer is one FMA:
+// v 2^40 + 1.5 2^52 rounds to an integer of the binade [2^52, 2^53), whose bit
+// pattern minus that of 1.5 2^52 is round(v 2^40).
 // 23 KB of LDS per capsule: several 256-thread workgroups share a CU, so the
 // capsules of a dense suspension run at once instead of in rounds.
 constexpr int kFxThreads = 256;
-constexpr int kFxBits = 50;          // resolution 2^-50 (8.9e-16)
-constexpr double kFxLimit = 1.0;     // |share component| limit, lattice units
+constexpr int kFxBits = 40;          // resolution 2^-40 (9.1e-13)
+constexpr double kFxLimit = 2048.0;  // |share component| limit, lattice units (2^11 = 2^(51-kFxBits))
 
 __device__ __forceinline__ long long fx_quant(const SimDev& S, double v) {
   if (!(fabs(v) < kFxLimit)) {
     atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
     v = isnan(v) ? 0.0 : copysign(kFxLimit, v);
   }
-  return __double_as_longlong(fma(v, 0x1p50, 0x1.8p52)) - __double_as_longlong(0x1.8p52);
+  return __double_as_longlong(fma(v, 0x1p40, 0x1.8p52)) - __double_as_longlong(0x1.8p52);
 }
 
 __device__ __forceinline__ void fx_add(long long* p, long long v) {
@@ -489,7 +494,7 @@ __device__ __forceinline__ void fx_add(long long* p, long long v) {
 }
 
 __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __restrict__ sims, Items it, int mode) {
-  static_assert(kFxBits == 50, "fx_quant and the readout scale by 2^50");
+  static_assert(kFxBits == 40, "fx_quant and the readout scale by 2^40");
   __shared__ long long acc[3][kLdsNodes];
   __shared__ BinTable bt;
   __shared__ uint32_t wmax;
@@ -540,7 +545,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
         double F[3], Xp[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          F[a] = act ? (double)acc[a][i] * 0x1p-50 : 0.0;
+          F[a] = act ? (double)acc[a][i] * 0x1p-40 : 0.0;
           Xp[a] = act ? X0[a * ms + i] : 0.0;
         }
         emit_nodes<float>(S, bt, L, act, off + i, Xp, F, mode, fbits);
@@ -550,7 +555,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
         double F[3], Xp[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          F[a] = (double)acc[a][i] * 0x1p-50;
+          F[a] = (double)acc[a][i] * 0x1p-40;
           Xp[a] = X0[a * ms + i];
         }
         emit_node<float>(S, L, off + i, Xp, F, mode, fbits);

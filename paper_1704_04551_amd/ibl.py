@@ -188,6 +188,11 @@ class Sim:
     def sync(self):
         _check(lib().ibl_sync(self.h))
 
+    def sync_status(self) -> int:
+        """Like sync(), but returns the status (0, or IBL_ERR_STATE / _UNSTABLE
+        from the health word) instead of raising."""
+        return int(lib().ibl_sync(self.h))
+
     @property
     def stream_handle(self) -> int:
         return lib().ibl_sim_stream(self.h)

@@ -8,6 +8,8 @@ per *chunk* of steps.  At every chunk boundary it
 
 1. retires the jobs that finished: reads their node positions, health word
    and conservation sums back to the host, then frees their device arena;
+   a job whose health word reports an unstable or invalid state (non-finite
+   values, a node outside the lattice) is retired at once as failed;
 2. admits queued jobs, first come first served, while their footprint
    (``ibl_sim_bytes``) fits in the free part of the memory pool and a slot is
    free; a job that can never fit is rejected, and arrivals beyond the queue
@@ -47,6 +49,7 @@ class Job:
     admitted: Optional[float] = None
     done: Optional[float] = None
     rejected: Optional[str] = None
+    failed: Optional[str] = None   # why a resident job was stopped (its health word)
     result: Optional[dict] = None
     handle: object = None      # backend simulation while resident
 
@@ -103,8 +106,12 @@ class GpuBackend:
         self._members = ()
 
     def wait(self, sims):
-        if sims:
-            sims[0].sync()
+        if sims:  # one stream for the batch; health is checked per job by failed()
+            sims[0].sync_status()
+
+    def failed(self, sim) -> Optional[str]:
+        st = sim.sync_status()
+        return None if st == 0 else {-4: "invalid state", -5: "unstable"}.get(st, "error %d" % st)
 
     def result(self, sim, spec) -> dict:
         mass, mom, health = sim.conservation()
@@ -146,6 +153,7 @@ class Server:
         self.resident: List[Job] = []
         self.finished: List[Job] = []
         self.rejected: List[Job] = []
+        self.failed: List[Job] = []
         self.used = 0
         self.peak_used = 0
         self.cell_steps = 0
@@ -177,7 +185,17 @@ class Server:
 
     def _retire(self, t0: float):
         keep = []
+        check = getattr(self.be, "failed", None)
         for job in self.resident:
+            why = check(job.handle) if check is not None else None
+            if why is not None:
+                job.failed = why
+                self.be.release(job.handle)
+                job.handle = None
+                self.used -= job.footprint
+                job.done = self.clock() - t0
+                self.failed.append(job)
+                continue
             if job.left > 0:
                 keep.append(job)
                 continue
@@ -237,6 +255,7 @@ class Server:
             "wall_s": wall,
             "finished": len(self.finished),
             "rejected": len(self.rejected),
+            "failed": len(self.failed),
             "unfinished": len(self.queue) + len(self.resident) + not_arrived,
             "p50_s": pct(50),
             "p99_s": pct(99),

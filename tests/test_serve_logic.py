@@ -138,6 +138,29 @@ def test_time_limit_and_stats():
     assert st["mlups"] > 0
 
 
+class FailingBackend(FakeBackend):
+    """Jobs whose spec sets `fail_at` report an unstable health word once they
+    have run that many steps."""
+
+    def failed(self, sim):
+        at = getattr(sim.spec, "fail_at", None)
+        return "unstable" if at is not None and sim.done >= at else None
+
+
+def test_unstable_job_is_retired_as_failed():
+    c = Clock()
+    be = FailingBackend(c)
+    srv = Server(be, 10 ** 7, chunk=10, max_resident=8, queue_cap=100, clock=c, sleep=c.sleep)
+    jobs = [Job(i, Spec(16, 50), arrival=0.0, steps=50) for i in range(4)]
+    jobs[2].spec.fail_at = 20
+    st = srv.run(jobs)
+    assert st["finished"] == 3 and st["failed"] == 1 and st["unfinished"] == 0
+    bad = srv.failed[0]
+    assert bad.jid == 2 and bad.failed == "unstable" and bad.result is None
+    assert be.live == set() and srv.used == 0  # its arena was released
+    assert all(j.result["steps"] == 50 for j in srv.finished)
+
+
 def test_bad_arguments():
     with pytest.raises(ValueError):
         Server(None, 0)
