@@ -169,9 +169,10 @@ def run_batched(storage, steps, skin):
             "batched_s": round(tb, 4), "plain_s": round(tp, 4), "bitwise_same": bool(same)}, xs
 
 
-def _serve(storage, jobs, pool, slots, queue_cap, time_limit):
+def _serve(storage, jobs, pool, slots, queue_cap, time_limit, skin):
     from paper_1704_04551_amd.serve import GpuBackend, Job, Server
-    srv = Server(GpuBackend(storage), pool_bytes=pool, chunk=100, max_resident=slots, queue_cap=queue_cap)
+    srv = Server(GpuBackend(storage, skin=skin), pool_bytes=pool, chunk=100, max_resident=slots,
+                 queue_cap=queue_cap)
     try:
         st = srv.run([Job(j.jid, j.spec, j.arrival, j.steps) for j in jobs], time_limit=time_limit)
     finally:
@@ -179,7 +180,7 @@ def _serve(storage, jobs, pool, slots, queue_cap, time_limit):
     return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
 
 
-def run_served(storage, seconds, rate, step_scale, seed=1005):
+def run_served(storage, seconds, rate, step_scale, skin, seed=1005):
     """Poisson arrivals of Jeffery-orbit jobs (ellipsoid of 642 nodes, ks
     0.05, AR 1.5-4, cubic lattice 48-128, shear rate 0.005, 2000-20000 steps)
     through the serving loop, `seconds` of arrivals per run:
@@ -201,21 +202,22 @@ def run_served(storage, seconds, rate, step_scale, seed=1005):
     pool = int(0.5 * free)
     edges = (48, 64, 80, 96, 112, 128)  # the job generator's lattice edges (uniform)
     mean_work = float(np.mean([e ** 3 for e in edges])) * (2000 + 20000) / 2.0
-    out = {"window_s": seconds, "pool_bytes": pool}
+    out = {"window_s": seconds, "pool_bytes": pool, "skin": skin}
     full = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, edges=edges), seed)
-    out["stated"] = dict(_serve(storage, full, pool, 64, 64, 3 * seconds), rate_jobs_s=rate, jobs=len(full))
+    out["stated"] = dict(_serve(storage, full, pool, 64, 64, 3 * seconds, skin), rate_jobs_s=rate,
+                         jobs=len(full))
     _log("served (stated rate): %s" % out["stated"])
     cap = out["stated"]["mlups"] * 1e6
     rate_s = 0.7 * cap / mean_work
     sus = poisson_jobs(rate_s, seconds, lambda rng: W.job_served(rng, edges=edges), seed + 1)
-    out["sustainable"] = dict(_serve(storage, sus, pool, 64, 4096, 10 * seconds),
+    out["sustainable"] = dict(_serve(storage, sus, pool, 64, 4096, 10 * seconds, skin),
                               rate_jobs_s=round(rate_s, 3), jobs=len(sus))
     _log("served (sustainable rate): %s" % out["sustainable"])
     lo, hi = max(1, int(2000 * step_scale)), max(1, int(20000 * step_scale))
     short = poisson_jobs(rate, seconds, lambda rng: W.job_served(rng, edges=edges, steps=(lo, hi)), seed)
     out["scaled"] = {"rate_jobs_s": rate, "jobs": len(short), "job_steps": [lo, hi]}
     for name, slots in (("batched", 64), ("plain", 1)):
-        out["scaled"][name] = _serve(storage, short, pool, slots, 4096, 3 * seconds)
+        out["scaled"][name] = _serve(storage, short, pool, slots, 4096, 3 * seconds, skin)
         _log("served (scaled jobs, %s): %s" % (name, out["scaled"][name]))
     out.update({"p50_s": out["sustainable"]["p50_s"], "p99_s": out["sustainable"]["p99_s"],
                 "capacity_mlups": out["stated"]["mlups"]})
@@ -339,6 +341,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=15.0, help="0 skips the served runs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
+    ap.add_argument("--serve-skin", type=int, default=1, choices=[0, 1],
+                    help="candidate-list skin of the served jobs")
     ap.add_argument("--cache", default=os.path.join(tempfile.gettempdir(), "ibl_rbc_channel_spec.npz"),
                     help="cache of the generated RBC node arrays ('' disables)")
     ap.add_argument("--precision-sweep", action="store_true",
@@ -455,7 +459,7 @@ def main():
     if args.serve_seconds > 0:
         _log("served: %.0f s of arrivals at %.1f jobs/s" % (args.serve_seconds, args.serve_rate))
         result["served"] = run_served(args.storage, args.serve_seconds, args.serve_rate,
-                                      args.serve_step_scale)
+                                      args.serve_step_scale, args.serve_skin)
         _log("served: %s" % result["served"])
     print(json.dumps(result), flush=True)
 
