@@ -40,8 +40,6 @@ ibl_status fail(ibl_status st, const std::string& msg) {
 
 constexpr int kGraphSteps = 16;
 
-// Force-kernel variant (tuning knob; IBL_FORCES=split selects the edge / node
-// split for every template, the default is one LDS workgroup per capsule).
 // Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x kBrickZ cells,
 // bs[0] the descriptor's brick_x, or by default the widest of 64, 32, 16 that
 // the x extent fills (long x rows keep the streaming accesses in whole cache
@@ -60,6 +58,10 @@ int log2i(int v) {
   return k;
 }
 
+// Force-kernel variant, a tuning knob read when a launch set is built: the
+// default is one LDS workgroup per capsule (fixed-point sums for FP32/FP16
+// storage); IBL_FORCES=split selects the edge / node split kernels for every
+// template, IBL_FORCES=shares the per-edge-share LDS kernel for FP32/FP16 too.
 int forces_variant() {
   const char* v = getenv("IBL_FORCES");
   if (v && strcmp(v, "split") == 0) return 1;
