@@ -31,8 +31,8 @@ def _record(name, **vals):
             fh.write(json.dumps(dict(test=name, **vals)) + "\n")
 
 
-def _run_pair(spec, storage, steps):
-    g = ibl.Sim.from_spec(spec, storage=storage)
+def _run_pair(spec, storage, steps, skin=0):
+    g = ibl.Sim.from_spec(spec, storage=storage, skin=skin)
     o = oracle_from_spec(spec)
     if steps:
         g.step(steps)
@@ -127,6 +127,39 @@ def test_small_couette_capsule_200_steps(storage, delta):
     spec = W.config_small(delta=delta)
     g, o = _run_pair(spec, storage, 200)
     _compare(spec, g, o, storage, name="small-couette-200-%s-%s" % (delta, storage))
+
+
+def _large_template_spec():
+    """40^3 Couette box (plates at -/+0.01 on z), one icosphere(4) capsule of
+    2562 nodes (more than one workgroup's force kernel takes: the edge / node
+    split kernels run) of radius 9 with jitter, ks 0.005, kb 0.001."""
+    rng = np.random.default_rng(91)
+    S, T = W.icosphere(4)
+    n = 40
+    x_ref = W.ellipsoid(S, 9.0, 9.0, 9.0) + (n - 1) / 2.0
+    x = x_ref + rng.normal(0.0, 0.01, size=x_ref.shape)
+    u_lo, u_hi = W._couette_walls(2, 0.01, -0.01)
+    return W.SimSpec(n=(n, n, n), tau=1.0, wall=(0, 0, 1), u_lo=u_lo, u_hi=u_hi, delta="cos",
+                     init_profile=1, capsules=[W.Capsule(x, x_ref, T, 0.005, 0.001, "big")], steps=100,
+                     name="large-template-40")
+
+
+@pytest.mark.parametrize("storage,skin", [("f64", 0), ("f32", 0), ("f32", 1)])
+def test_large_template_split_kernels(storage, skin):
+    spec = _large_template_spec()
+    assert spec.nodes == 2562
+    g, o = _run_pair(spec, storage, 100, skin)
+    _compare(spec, g, o, storage, name="large-template-100-%s-skin%d" % (storage, skin))
+
+
+@pytest.mark.parametrize("variant", ["split", "shares"])
+def test_force_kernel_variants(variant, monkeypatch):
+    """The alternative force kernels (edge / node split; per-edge float shares
+    in LDS) on the small Couette capsule against the oracle."""
+    monkeypatch.setenv("IBL_FORCES", variant)
+    spec = W.config_small(delta="cos")
+    g, o = _run_pair(spec, "f32", 200)
+    _compare(spec, g, o, "f32", name="small-couette-200-cos-f32-" + variant)
 
 
 def _ragged_spec():
