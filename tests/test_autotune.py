@@ -47,7 +47,8 @@ def test_memo_skips_retiming():
 
 
 @pytest.mark.gpu
-def test_every_shape_is_bitwise_identical():
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_every_shape_is_bitwise_identical(storage):
     """Brick width and list skin change only how the work is split: the
     spreading sums are exact fixed-point sums with one scale per simulation,
     so fields and node positions are bitwise identical for every pair, also
@@ -57,7 +58,7 @@ def test_every_shape_is_bitwise_identical():
     out = {}
     for bx in (16, 32, 64):
         for skin in (0, 1):
-            s = ibl.Sim.from_spec(spec, storage="f32", brick_x=bx, skin=skin)
+            s = ibl.Sim.from_spec(spec, storage=storage, brick_x=bx, skin=skin)
             s.step(700)
             s.sync()
             out[(bx, skin)] = (s.fields(rho=False, g=False)[1], s.nodes(0)[0])
