@@ -224,8 +224,8 @@ struct ibl_batch_s {
 namespace {
 
 void drop_graphs(hipGraphExec_t& g1, hipGraphExec_t& gN) {
-  if (g1) hipGraphExecDestroy(g1);
-  if (gN) hipGraphExecDestroy(gN);
+  if (g1) (void)hipGraphExecDestroy(g1);
+  if (gN) (void)hipGraphExecDestroy(gN);
   g1 = gN = nullptr;
 }
 
@@ -238,12 +238,12 @@ ibl_status capture(int storage, const SimDev* sims, const Items& it, hipStream_t
   le = launch_steps(storage, sims, it, steps, 0, s);
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
-    if (graph) hipGraphDestroy(graph);
+    if (graph) (void)hipGraphDestroy(graph);
     return fail(IBL_ERR_DEVICE, std::string("launch during capture: ") + hipGetErrorString(le));
   }
   if (ce != hipSuccess) return fail(IBL_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
   hipError_t ie = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
-  hipGraphDestroy(graph);
+  (void)hipGraphDestroy(graph);
   if (ie != hipSuccess) return fail(IBL_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
   return IBL_OK;
 }
@@ -349,11 +349,13 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   Layout L = make_layout(desc);
   if (arena_bytes < L.total) return fail(IBL_ERR_NOMEM, "arena smaller than ibl_sim_bytes");
   if (((uintptr_t)dev_arena) % 256 != 0) return fail(IBL_ERR_ARG, "arena must be 256-byte aligned");
+  int device = 0;
+  HIPCHK(hipGetDevice(&device));
   ibl_sim S = new ibl_sim_s();
   S->desc = *desc;
   S->arena = (char*)dev_arena;
   S->L = L;
-  hipGetDevice(&S->device);
+  S->device = device;
   if (hip_stream) {
     S->stream = (hipStream_t)hip_stream;
   } else {
@@ -440,7 +442,7 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
     if (e != hipSuccess) st = fail(IBL_ERR_DEVICE, std::string("init: ") + hipGetErrorString(e));
   }
   if (st) {
-    if (S->own_stream) hipStreamDestroy(S->stream);
+    if (S->own_stream) (void)hipStreamDestroy(S->stream);
     delete S;
     return st;
   }
@@ -450,10 +452,10 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
 
 ibl_status ibl_sim_destroy(ibl_sim S) {
   if (!S) return IBL_OK;
-  hipSetDevice(S->device);
-  hipStreamSynchronize(S->stream);
+  (void)hipSetDevice(S->device);  // teardown: nothing to report to
+  (void)hipStreamSynchronize(S->stream);
   drop_graphs(S->g1, S->gN);
-  if (S->own_stream) hipStreamDestroy(S->stream);
+  if (S->own_stream) (void)hipStreamDestroy(S->stream);
   delete S;
   return IBL_OK;
 }
@@ -525,7 +527,7 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   if (S->ntmpl + 1 > S->desc.max_templates || S->tnodes + nn > S->desc.max_template_nodes ||
       S->tedges + ne > S->desc.max_template_edges)
     return fail(IBL_ERR_NOMEM, "template capacity exceeded");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   const int e0 = S->tedges, n0 = S->tnodes;
   // incidence CSR rows of this template's nodes (global edge indices)
   std::vector<std::vector<int>> rows(nn);
@@ -581,7 +583,7 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
       if (S->desc.wall[a] && !(v >= 1.0 && v < (double)(S->desc.n[a] - 2)))
         return fail(IBL_ERR_ARG, "node outside 1 <= X < n-2 on a wall axis");
     }
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   const int off = S->nnodes;
   const size_t ms = (size_t)S->desc.max_nodes;
   const std::vector<int>& perm = S->t_perm[tmpl];
@@ -611,7 +613,7 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
 ibl_status ibl_step(ibl_sim S, int64_t n) {
   if (!S || n < 0) return fail(IBL_ERR_ARG, "bad argument");
   if (n == 0) return IBL_OK;
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, S->stream, S->hd.remaining, n);
   HIPCHK(hipGetLastError());
   return run_steps(S->desc.storage, S->dd, S->items, S->stream, S->g1, S->gN, n);
@@ -619,7 +621,7 @@ ibl_status ibl_step(ibl_sim S, int64_t n) {
 
 ibl_status ibl_sync(ibl_sim S) {
   if (!S) return fail(IBL_ERR_ARG, "null simulation");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   HIPCHK(hipStreamSynchronize(S->stream));
   uint32_t h = 0;
   HIPCHK(hipMemcpy(&h, S->hd.health, 4, hipMemcpyDeviceToHost));
@@ -627,7 +629,7 @@ ibl_status ibl_sync(ibl_sim S) {
 }
 
 static ibl_status observe(ibl_sim S) {
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   HIPCHK(launch_steps(S->desc.storage, S->dd, S->items, 1, 1, S->stream));
   HIPCHK(hipStreamSynchronize(S->stream));
   return IBL_OK;
@@ -694,7 +696,7 @@ ibl_status ibl_read_nodes(ibl_sim S, int32_t mesh, double* x, double* u, double*
 
 ibl_status ibl_conservation(ibl_sim S, double* mass, double momentum[3], uint32_t* health) {
   if (!S) return fail(IBL_ERR_ARG, "null simulation");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   HIPCHK(launch_reduce(S->desc.storage, S->dd, S->items, S->stream));
   double out[4];
   uint32_t h = 0;
@@ -710,7 +712,7 @@ ibl_status ibl_conservation(ibl_sim S, double* mass, double momentum[3], uint32_
 
 ibl_status ibl_step_count(ibl_sim S, int64_t* out) {
   if (!S || !out) return fail(IBL_ERR_ARG, "null argument");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   HIPCHK(hipStreamSynchronize(S->stream));
   HIPCHK(hipMemcpy(out, S->hd.step, 8, hipMemcpyDeviceToHost));
   return IBL_OK;
@@ -769,7 +771,7 @@ ibl_status ibl_write_state(ibl_sim S, const void* buf, size_t bytes) {
   if (memcmp(h.magic, "IBLSTAT1", 8) != 0 || h.storage != S->desc.storage || h.nnodes != S->nnodes ||
       h.n[0] != S->desc.n[0] || h.n[1] != S->desc.n[1] || h.n[2] != S->desc.n[2] || h.step < 0)
     return fail(IBL_ERR_ARG, "state does not match this simulation");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   HIPCHK(hipStreamSynchronize(S->stream));
   const char* p = (const char*)buf + sizeof(h);
   const size_t fb = (size_t)kQ * S->L.ncell * storage_bytes(S->desc.storage);
@@ -787,7 +789,7 @@ ibl_status ibl_write_state(ibl_sim S, const void* buf, size_t bytes) {
 
 ibl_status ibl_profile_phases(ibl_sim S, int64_t n, double* ms) {
   if (!S || !ms || n <= 0 || n > 100000) return fail(IBL_ERR_ARG, "bad argument");
-  hipSetDevice(S->device);
+  HIPCHK(hipSetDevice(S->device));
   const int np = kNumPhases;
   std::vector<hipEvent_t> ev((size_t)n * np + 1, nullptr);
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
@@ -810,7 +812,7 @@ ibl_status ibl_profile_phases(ibl_sim S, int64_t n, double* ms) {
   float tot = 0.f;
   if (!err) err = hipEventElapsedTime(&tot, ev[0], ev[(size_t)n * np]);
   ms[np] = tot;
-  for (auto& e : ev) hipEventDestroy(e);
+  for (auto& e : ev) (void)hipEventDestroy(e);
   if (err) return fail(IBL_ERR_DEVICE, std::string("phase profile: ") + hipGetErrorString(err));
   return IBL_OK;
 }
@@ -824,7 +826,7 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
     for (int j = 0; j < i; ++j)
       if (sims[j] == sims[i]) return fail(IBL_ERR_ARG, "simulation listed twice");
   }
-  hipSetDevice(sims[0]->device);
+  HIPCHK(hipSetDevice(sims[0]->device));
   ibl_batch B = new ibl_batch_s();
   B->sims.assign(sims, sims + n);
   B->storage = sims[0]->desc.storage;
@@ -850,8 +852,8 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   if (!e) e = hipMemcpy(B->doffs, offs.data(), offs.size() * 4, hipMemcpyHostToDevice);
   if (!e) e = hipEventCreateWithFlags(&B->ev, hipEventDisableTiming);
   if (e) {
-    hipFree(B->dsims);
-    hipFree(B->doffs);
+    (void)hipFree(B->dsims);
+    (void)hipFree(B->doffs);
     delete B;
     return fail(IBL_ERR_DEVICE, std::string("batch tables: ") + hipGetErrorString(e));
   }
@@ -881,7 +883,7 @@ ibl_status ibl_batch_step(ibl_batch B, const int64_t* steps) {
     if (steps[i] < 0) return fail(IBL_ERR_ARG, "negative step count");
     nmax = steps[i] > nmax ? steps[i] : nmax;
   }
-  hipSetDevice(B->sims[0]->device);
+  HIPCHK(hipSetDevice(B->sims[0]->device));
   // order the batch stream after pending work of the members' own streams
   for (int i = 1; i < n; ++i)
     if (B->sims[i]->stream != B->stream) {
@@ -908,12 +910,12 @@ ibl_status ibl_batch_step(ibl_batch B, const int64_t* steps) {
 
 ibl_status ibl_batch_destroy(ibl_batch B) {
   if (!B) return IBL_OK;
-  hipSetDevice(B->sims[0]->device);
-  hipStreamSynchronize(B->stream);
+  (void)hipSetDevice(B->sims[0]->device);  // teardown: nothing to report to
+  (void)hipStreamSynchronize(B->stream);
   drop_graphs(B->g1, B->gN);
-  hipFree(B->dsims);
-  hipFree(B->doffs);
-  hipEventDestroy(B->ev);
+  (void)hipFree(B->dsims);
+  (void)hipFree(B->doffs);
+  (void)hipEventDestroy(B->ev);
   delete B;
   return IBL_OK;
 }
