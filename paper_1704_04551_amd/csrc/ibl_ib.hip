@@ -763,13 +763,10 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
     const int oz = (int)(r / S.nq[1]) << kCubeShift[2];
     const GLB NodeRec<R>* rec = (const GLB NodeRec<R>*)S.rec;
     const GLB int32_t* list = S.hlist + h * kHomeCap;
-    // this lane's first node, fetched before the tile so both are in flight
-    int node = -1;
+    // this lane's first list entry, then the tile's loads, then the entry's
+    // record: the tile loads do not wait for the list entry
+    int node = tid < cnt ? list[tid] : -1;
     NodeRec<R> q;
-    if (tid < cnt) {
-      node = list[tid];
-      q = *(const NodeRec<R>*)(rec + node);
-    }
     const GLB R* uf = (const GLB R*)S.u;  // [3][ncell]
     const uint32_t ncl = (uint32_t)S.ncell;
     // the tile's loads are issued in batches of kBatch per lane before their
@@ -796,6 +793,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
           v[k][2] = uf[2 * ncl + c];
         }
       }
+      if (k0 == 0 && node >= 0) q = *(const NodeRec<R>*)(rec + node);
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
         const int t = tid + (k0 + k) * kInterpThreads;
