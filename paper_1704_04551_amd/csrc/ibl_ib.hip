@@ -680,7 +680,8 @@ __device__ __forceinline__ int margin_wrap(int c, int n) {
 
 template <typename R>
 __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCubeTile], const NodeRec<R>& q,
-                                            int node, int ox, int oy, int oz, int mode, int next_par) {
+                                            int node, const double X0[3], int ox, int oy, int oz, int mode,
+                                            int next_par) {
   constexpr int ex = (1 << kCubeShift[0]) + 3, exy = ex * ((1 << kCubeShift[1]) + 3);
   // tile index of stencil point (0, 0, 0): base - 1 relative to o - 1
   const int t0 = (q.base[0] - ox) + ex * (q.base[1] - oy) + exy * (q.base[2] - oz);
@@ -704,11 +705,11 @@ __device__ __forceinline__ void interp_node(const SimDev& S, const R (*ut)[kCube
   const int64_t ms = (int64_t)S.maxn;
   const double ux = (double)sx, uy = (double)sy, uz = (double)sz;
   if (mode == 0 && S.skin == 0) {
-    S.X[node] += ux;
-    S.X[ms + node] += uy;
-    S.X[2 * ms + node] += uz;
+    S.X[node] = X0[0] + ux;
+    S.X[ms + node] = X0[1] + uy;
+    S.X[2 * ms + node] = X0[2] + uz;
   } else if (mode == 0) {
-    const double xn[3] = {S.X[node] + ux, S.X[ms + node] + uy, S.X[2 * ms + node] + uz};
+    const double xn[3] = {X0[0] + ux, X0[1] + uy, X0[2] + uz};
     S.X[node] = xn[0];
     S.X[ms + node] = xn[1];
     S.X[2 * ms + node] = xn[2];
@@ -767,6 +768,8 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
     // record: the tile loads do not wait for the list entry
     int node = tid < cnt ? list[tid] : -1;
     NodeRec<R> q;
+    double X0[3] = {0.0, 0.0, 0.0};  // the node's position (step mode), loaded with its record
+    const int64_t ms = (int64_t)S.maxn;
     const GLB R* uf = (const GLB R*)S.u;  // [3][ncell]
     const uint32_t ncl = (uint32_t)S.ncell;
     // the tile's loads are issued in batches of kBatch per lane before their
@@ -793,7 +796,14 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
           v[k][2] = uf[2 * ncl + c];
         }
       }
-      if (k0 == 0 && node >= 0) q = *(const NodeRec<R>*)(rec + node);
+      if (k0 == 0 && node >= 0) {
+        q = *(const NodeRec<R>*)(rec + node);
+        if (mode == 0) {
+          X0[0] = S.X[node];
+          X0[1] = S.X[ms + node];
+          X0[2] = S.X[2 * ms + node];
+        }
+      }
 #pragma unroll
       for (int k = 0; k < kBatch; ++k) {
         const int t = tid + (k0 + k) * kInterpThreads;
@@ -812,9 +822,14 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(const SimDev* __restr
         if (i0 + tid < cnt) {
           node = list[i0 + tid];
           q = *(const NodeRec<R>*)(rec + node);
+          if (mode == 0) {
+            X0[0] = S.X[node];
+            X0[1] = S.X[ms + node];
+            X0[2] = S.X[2 * ms + node];
+          }
         }
       }
-      if (node >= 0) interp_node<R>(S, ut, q, node, ox, oy, oz, mode, next_par);
+      if (node >= 0) interp_node<R>(S, ut, q, node, X0, ox, oy, oz, mode, next_par);
     }
     __syncthreads();
     if (tid == 0) S.hcount[h] = 0;
