@@ -360,13 +360,14 @@ __device__ __forceinline__ void clear_next_rebuild(const SimDev& S, const ListSt
 }
 
 // ------------------------------------------------------------ forces (LDS) --
-// Per-edge force shares are computed in FP64 and kept in LDS in the
-// precision of the spreading record R (double for FP64 storage, float
-// otherwise: the shares then carry ~1e-7 relative rounding, far below the
-// FP32 path's own error).  Vertex positions are read from global memory (one
-// capsule's positions stay in L2).  Float shares need 69 KB of LDS, so two
-// 512-thread workgroups share a CU; double shares take one 1024-thread
-// workgroup per CU.  Each thread gathers up to two nodes.
+// FP64 storage (and, as a tuning alternative, FP32 / FP16 storage): per-edge
+// force shares are computed in FP64 and kept in LDS in the precision of the
+// spreading record R (double for FP64 storage; float otherwise, where the
+// shares carry ~1e-7 relative rounding, far below the FP32 path's own error).
+// Vertex positions are read from global memory (one capsule's positions stay
+// in L2).  Float shares need 69 KB of LDS, so two 512-thread workgroups share
+// a CU; double shares take one 1024-thread workgroup per CU.  Each thread
+// gathers up to two nodes.
 template <typename R>
 constexpr int forces_threads() { return sizeof(R) == 4 ? 512 : 1024; }
 static_assert(2 * 512 >= kLdsNodes, "two nodes per thread cover a template of the LDS force kernel");
@@ -475,7 +476,7 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
 // 2^(63-kFxBits).  With |v 2^40| < 2^51 the rounding to an integer is one FMA:
 // v 2^40 + 1.5 2^52 rounds to an integer of the binade [2^52, 2^53), whose bit
 // pattern minus that of 1.5 2^52 is round(v 2^40).
-// 23 KB of LDS per capsule: several 256-thread workgroups share a CU, so the
+// 21.5 KB of LDS per capsule: five 256-thread workgroups share a CU, so the
 // capsules of a dense suspension run at once instead of in rounds.
 constexpr int kFxThreads = 256;
 constexpr int kFxBits = 40;          // resolution 2^-40 (9.1e-13)
