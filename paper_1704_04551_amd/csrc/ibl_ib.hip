@@ -1,20 +1,25 @@
 // Immersed-boundary kernels of the coupled step (Sec. 2.2-2.3):
 //
-//   k_edge_forces / k_node_forces  (templates larger than the LDS kernel
+//   k_forces_fx   (FP32 / FP16 storage) one workgroup per capsule: every
+//                 edge's spring + bending shares on its four vertices (FP64)
+//                 are summed per node in LDS as 64-bit fixed-point integers.
+//   k_forces_lds  (FP64 storage) one workgroup per capsule: every edge's
+//                 shares are kept in LDS and each node gathers its incident
+//                 shares in a fixed order.
+//   k_edge_forces / k_node_forces  (templates larger than one workgroup
 //                 takes) every edge of every capsule in parallel (FP64 shares
 //                 to scratch), then every node gathers its incident shares in a
-//                 fixed order and writes its record.
-//   k_forces_lds  one workgroup per capsule.  Every edge's spring + bending
-//                 forces on its four vertices are computed once (FP64) into
-//                 LDS; each node then gathers its incident edge shares in a
-//                 fixed order.  Writes F, the node's spreading record (stencil
-//                 base, delta weights, F) and appends the node to the
-//                 candidate lists of the lattice bricks its 4x4x4 stencil
-//                 touches.
+//                 fixed order.
+//   Each force kernel writes the node's spreading record (stencil base,
+//   fractional offset or delta weights, F), adds the step's largest force
+//   component to the simulation's maximum, and appends the node to the
+//   candidate lists of the lattice bricks its 4x4x4 stencil touches: every
+//   step, or with a one-cell skin only when the lists are rebuilt.
 //   k_interp      Eq. (14): one workgroup per home cube (16 x 8 x 8 cells),
 //                 the cube's velocity and its stencil margin in LDS, one lane
 //                 per home node, fixed summation order; X^{n+1} = X^n + U
-//                 (FP64).  Clears the cube's node list.
+//                 (FP64).  Clears the cube's node list; with a skin, flags a
+//                 rebuild when a node leaves it.
 // Force spreading (Eq. (15)) runs per brick inside the collide-stream kernel
 // (ibl_kernels.hip), from the candidate lists written here.
 #include "ibl_device.h"
