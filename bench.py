@@ -368,7 +368,7 @@ def main():
         precision_sweep(args)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only; --gpus %d is not supported "
+        print("bench.py: runs on one GPU only; --gpus %d is not supported "
               "(the multi-GPU slab decomposition is a design, not built)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)

@@ -50,7 +50,7 @@ typedef enum {
   IBL_ERR_DEVICE = -3,      /* a HIP runtime call failed */
   IBL_ERR_STATE = -4,       /* a node left the admissible range / list overflow */
   IBL_ERR_UNSTABLE = -5,    /* non-finite populations or node positions, rho <= 0 */
-  IBL_ERR_UNSUPPORTED = -6  /* valid request this build does not implement */
+  IBL_ERR_UNSUPPORTED = -6  /* valid request that this library does not implement */
 } ibl_status;
 
 /* Population storage.  Every mode stores the offset of each population from
