@@ -10,7 +10,8 @@
 //              bounce-back (moving-wall term); u^n is written for the
 //              interpolation.  The force field never leaves LDS.
 //   k_interp   velocity interpolation and node update (ibl_ib.hip)
-//   k_advance  per simulation: step counter (A/B parity) and remaining steps.
+//   k_advance  per simulation, after a captured sequence of steps: step
+//              counter (A/B parity) and remaining steps.
 // Every kernel walks a flattened (simulation, work item) list, so one launch
 // serves a single simulation or a batch of uneven ones.
 #include "ibl_device.h"
@@ -212,10 +213,10 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
 
 // -------------------------------------------------------------- lattice --
 // Fixed-point accumulator of the spread force: every share w F is scaled by
-// 2^s, s = kBits - e where 2^e bounds the largest force component among the
-// brick's candidates (collected as an order-independent integer max of float
-// bits when the nodes were appended), rounded to the nearest integer and
-// added with an integer LDS atomic.  Integer addition is associative, so the
+// 2^s, s = kBits - e where 2^e bounds the step's largest force component in
+// the simulation (collected by the force kernels as an order-independent
+// integer max of float bits), rounded to the nearest integer and added with
+// an integer LDS atomic.  Integer addition is associative, so the
 // per-cell sums are exact and identical whatever order the lanes and waves
 // run in: bitwise reproducible without sorting.  Resolution max|F| 2^-kBits
 // (below the rounding of one share in the compute precision); headroom 2^4
