@@ -98,7 +98,8 @@ typedef struct {
   int32_t max_template_nodes; /* capacity: nodes summed over templates */
   int32_t max_template_edges; /* capacity: edges summed over templates */
   int32_t brick_x;         /* lattice brick width along x: 16, 32 or 64 cells (bricks are
-                              brick_x x 256/brick_x x 4 cells, one workgroup each), or 0
+                              brick_x x 256/brick_x x 4 cells, 8 deep for FP16 storage,
+                              one workgroup each), or 0
                               for the widest that the x extent fills.  A tuning knob:
                               results are bitwise identical across widths. */
   int32_t skin;            /* candidate lists of the spreading (node binning): 0 rebuilds

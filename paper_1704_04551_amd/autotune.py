@@ -1,13 +1,14 @@
 """Autotuner of the lattice brick shape and the candidate-list skin.
 
 The collide-stream kernel processes the lattice in bricks of
-``brick_x x (256 / brick_x) x 4`` cells, one workgroup each, and spreads the
+``brick_x x (256 / brick_x) x d`` cells (d = 4, or 8 for FP16 storage), one
+workgroup each, and spreads the
 brick's candidate nodes into LDS first.  Two knobs trade against each other:
 
 * the brick width: long x rows keep the streaming accesses in whole cache
   lines; narrow bricks are taller, so fewer nodes straddle a brick boundary
   (the candidate region of a brick is (brick_x + 3 + 2 skin) x
-  (256 / brick_x + 3 + 2 skin) x (7 + 2 skin) cells);
+  (256 / brick_x + 3 + 2 skin) x (d + 3 + 2 skin) cells);
 * the skin: without one (0) the force kernel rebuilds every brick's
   candidate list each step; with a one-cell skin (1) the lists are kept until
   some node has moved a cell, which saves most of the list building but

@@ -19,12 +19,11 @@
 namespace ibl {
 
 constexpr int kQ = 19;
-// The lattice is processed in bricks of bs[0] x bs[1] x kBrickZ cells with
+// The lattice is processed in bricks of bs[0] x bs[1] x bs[2] cells with
 // bs[0] x bs[1] = kBrickThreads: one workgroup per brick, each thread a column
-// of kBrickZ cells.  bs[0] (16, 32 or 64) is chosen per simulation.
+// of bs[2] cells (brick_depth of the storage mode).  bs[0] (16, 32 or 64) is
+// chosen per simulation.
 constexpr int kBrickThreads = 256;
-constexpr int kBrickZ = 4;
-constexpr int kBrickCells = kBrickThreads * kBrickZ;
 constexpr int kCandCap = 4096;       // candidate nodes per brick
 // Candidate lists are rebuilt every step (skin 0), or built with a skin of
 // `skin` cells around each node's stencil and kept while every node's stencil
@@ -54,6 +53,12 @@ __host__ __device__ constexpr double wq(int i) {
 }
 
 enum Storage : int { kF64 = 0, kF32 = 1, kF16 = 2 };
+
+// Cells per thread column of a brick.  FP16 storage streams half the bytes,
+// so a brick's spreading phase hides less behind the other workgroups'
+// streaming: its bricks are twice as deep (and its spread-force field packs
+// three sums per word, so the LDS still holds five workgroups per CU).
+constexpr int brick_depth(int storage) { return storage == kF16 ? 8 : 4; }
 enum Delta : int { kCos = 0, kPeskin4 = 1 };
 
 enum Health : uint32_t {

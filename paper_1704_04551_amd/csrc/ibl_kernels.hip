@@ -14,6 +14,8 @@
 //              counter (A/B parity) and remaining steps.
 // Every kernel walks a flattened (simulation, work item) list, so one launch
 // serves a single simulation or a batch of uneven ones.
+#include <type_traits>
+
 #include "ibl_device.h"
 
 namespace ibl {
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     brick_origin(S, b, ox, oy, oz);
     const int x = ox + (tid & (S.bs[0] - 1)), y = oy + (tid >> S.bsh[0]);
     if (x >= S.n[0] || y >= S.n[1]) continue;
-    for (int k = 0; k < kBrickZ && oz + k < S.n[2]; ++k) init_cell<ST>(S, x, y, oz + k, profile);
+    for (int k = 0; k < brick_depth(ST) && oz + k < S.n[2]; ++k) init_cell<ST>(S, x, y, oz + k, profile);
   }
 }
 
@@ -220,21 +222,27 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
 // per-cell sums are exact and identical whatever order the lanes and waves
 // run in: bitwise reproducible without sorting.  Resolution max|F| 2^-kBits
 // (below the rounding of one share in the compute precision); headroom 2^4
-// (31 - 27, 63 - 58) times max|F| per cell, while the delta kernel's
+// (31 - 27, 63 - 58, 20 - 16) times max|F| per cell, while the delta kernel's
 // partition of unity bounds a cell's sum by max|F| times the nodes per cell.
 //
-// FP32 / FP16: the x and y sums share one 64-bit word, y 2^32 + x, so one
-// 64-bit atomic adds both (z takes a 32-bit one).  The word's sum is exactly
+// FP32: the x and y sums share one 64-bit word, y 2^32 + x, so one 64-bit
+// atomic adds both (z takes a 32-bit one).  The word's sum is exactly
 // (sum y) 2^32 + (sum x); the low 32 bits, sign-extended, give sum x as long
 // as it fits in 32 bits (the headroom above), and the rest gives sum y.
+//
+// FP16 storage: all three sums share one 64-bit word in 21-bit fields,
+// z 2^42 + y 2^21 + x, with kBits = 16 (8 B per cell, for bricks twice as
+// deep).  The resolution, 2^-16 of the step's largest force, is far below
+// the binary16 rounding of the populations that the force feeds.
 template <typename R>
 struct FixAcc;
 template <>
 struct FixAcc<float> {
   static constexpr int kBits = 27;
+  static constexpr int kCells = kBrickThreads * brick_depth(kF32);
   struct Field {
-    long long xy[kBrickCells];
-    int32_t z[kBrickCells];
+    long long xy[kCells];
+    int32_t z[kCells];
   };
   __device__ static void clear(Field& f, int li) {
     f.xy[li] = 0;
@@ -253,11 +261,38 @@ struct FixAcc<float> {
     gz = (float)f.z[li] * inv;
   }
 };
+struct FixAcc3 {
+  static constexpr int kBits = 16;
+  static constexpr int kCells = kBrickThreads * brick_depth(kF16);
+  static constexpr long long kF = 1LL << 21;  // field unit
+  struct Field {
+    long long xyz[kCells];
+  };
+  __device__ static void clear(Field& f, int li) { f.xyz[li] = 0; }
+  __device__ static void add(Field& f, int li, float gx, float gy, float gz) {
+    const long long w = (long long)__float2int_rn(gz) * (kF * kF) + (long long)__float2int_rn(gy) * kF +
+                        (long long)__float2int_rn(gx);
+    atomicAdd((unsigned long long*)&f.xyz[li], (unsigned long long)w);
+  }
+  // low 21 bits as a signed field
+  __device__ static long long field(long long w) { return ((w & (kF - 1)) ^ (kF >> 1)) - (kF >> 1); }
+  __device__ static void get(const Field& f, int li, float inv, float& gx, float& gy, float& gz) {
+    long long w = f.xyz[li];
+    const long long x = field(w);
+    w = (w - x) / kF;  // exact: w - x is a multiple of 2^21
+    const long long y = field(w);
+    const long long z = (w - y) / kF;
+    gx = (float)x * inv;
+    gy = (float)y * inv;
+    gz = (float)z * inv;
+  }
+};
 template <>
 struct FixAcc<double> {
   static constexpr int kBits = 58;
+  static constexpr int kCells = kBrickThreads * brick_depth(kF64);
   struct Field {
-    long long c[3][kBrickCells];
+    long long c[3][kCells];
   };
   __device__ static void clear(Field& f, int li) { f.c[0][li] = f.c[1][li] = f.c[2][li] = 0; }
   __device__ static void add(Field& f, int li, double gx, double gy, double gz) {
@@ -280,7 +315,9 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
-  using FA = FixAcc<R>;
+  using FA = typename std::conditional<ST == kF16, FixAcc3, FixAcc<R>>::type;
+  constexpr int BZ = brick_depth(ST);
+  static_assert(FA::kCells == kBrickThreads * BZ, "spread-force field of one brick");
   __shared__ typename FA::Field gq;
   // home-cube lists: the brick's home candidates (base cell inside the brick)
   // counted per cube (a brick meets at most 4 cubes: 64 x 4 -> 4 x 1,
@@ -326,7 +363,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       NodeRec<R> q;
       if (tid < cnt) q = *(const NodeRec<R>*)(rec + list[tid]);
 #pragma unroll
-      for (int k = 0; k < kBrickZ; ++k) FA::clear(gq, tid + kBrickThreads * k);
+      for (int k = 0; k < BZ; ++k) FA::clear(gq, tid + kBrickThreads * k);
       if (tid < 4) hc[tid] = 0;
       // cubes the brick meets: nlx along x by (at most 2) along y
       const int nlx = bx >> kCubeShift[0] > 0 ? bx >> kCubeShift[0] : 1;
@@ -400,7 +437,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         S.fmax[par ^ 1] = 0u;  // the next step's maximum starts from zero
       }
     }
-    // ---- collide-stream, a column of kBrickZ cells per thread
+    // ---- collide-stream, a column of BZ cells per thread
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
     if (x < nx && y < ny) {
       const int64_t nc = S.ncell;
@@ -411,7 +448,7 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       const R om = (R)(1.0 / S.tau);
       const R pre = (R)(1.0 - 0.5 / S.tau);
 #pragma unroll 1
-      for (int k = 0; k < kBrickZ; ++k) {
+      for (int k = 0; k < BZ; ++k) {
         const int z = oz + k;
         if (z >= nz) break;
         const int64_t cell = x + (int64_t)nx * (y + (int64_t)ny * z);

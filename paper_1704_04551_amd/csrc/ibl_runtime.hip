@@ -40,7 +40,7 @@ ibl_status fail(ibl_status st, const std::string& msg) {
 
 constexpr int kGraphSteps = 16;
 
-// Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x kBrickZ cells,
+// Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x brick_depth cells,
 // bs[0] the descriptor's brick_x, or by default the widest of 64, 32, 16 that
 // the x extent fills (long x rows keep the streaming accesses in whole cache
 // lines).
@@ -49,7 +49,7 @@ void brick_shape(const ibl_sim_desc* d, int bs[3]) {
   if (d->brick_x) bx = d->brick_x;
   bs[0] = bx;
   bs[1] = kBrickThreads / bx;
-  bs[2] = kBrickZ;
+  bs[2] = brick_depth(d->storage);
 }
 
 int log2i(int v) {
