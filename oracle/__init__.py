@@ -53,6 +53,12 @@ def lib():
         L.oracle_phi.argtypes = [I, D]
         L.oracle_membrane.restype = I
         L.oracle_membrane.argtypes = [I, I, P, P, P, D, D, P, P]
+        L.oracle_membrane_full.restype = I
+        L.oracle_membrane_full.argtypes = [I, I, P, P, P, D, D, D, D, D, D, P, P]
+        L.oracle_template_rest.restype = I
+        L.oracle_template_rest.argtypes = [I, I, P, P, P, P, P]
+        L.oracle_mesh_membrane.restype = I
+        L.oracle_mesh_membrane.argtypes = [P, I, D, D, D, D]
         L.oracle_mesh_edges.restype = I
         L.oracle_mesh_edges.argtypes = [I, I, P, P, P, P, P]
         L.oracle_spread_field.restype = I
@@ -119,6 +125,38 @@ def membrane(tris, x_ref, x, ks, kb):
     if ne < 0:
         raise ValueError("mesh is not a closed, consistently oriented manifold")
     return F, float(E[0])
+
+
+def membrane_full(tris, x_ref, x, ks, kb, kbtp=0.0, kg=0.0, kl=0.0, kv=0.0):
+    """Force (n,3) and energy of the paper's membrane energy, Eq. (6): linear
+    springs (ks) and dihedral bending (kb) as in `membrane`, plus WLC-POW
+    stretching (kbtp = kBT/p, Eq. (7)), global / local area (kg, kl, Eq. (9))
+    and volume (kv, Eq. (10)) constraints, rest state from x_ref."""
+    tris = _i32(tris)
+    x_ref = _f64(x_ref)
+    x = _f64(x)
+    F = np.zeros_like(x)
+    E = np.zeros(1)
+    r = lib().oracle_membrane_full(x.shape[0], tris.shape[0], _p(tris), _p(x_ref), _p(x), ks, kb,
+                                   kbtp, kg, kl, kv, _p(F), _p(E))
+    if r == -1:
+        raise ValueError("mesh is not a closed, consistently oriented manifold")
+    if r == -2:
+        raise ValueError("a bond reached its maximum length")
+    return F, float(E[0])
+
+
+def template_rest(tris, x_ref):
+    """(per-triangle rest areas (nt,), total rest area A0, rest volume V0)."""
+    tris = _i32(tris)
+    x_ref = _f64(x_ref)
+    a0 = np.zeros(tris.shape[0])
+    A0 = np.zeros(1)
+    V0 = np.zeros(1)
+    if lib().oracle_template_rest(x_ref.shape[0], tris.shape[0], _p(tris), _p(x_ref), _p(a0),
+                                  _p(A0), _p(V0)) != 0:
+        raise ValueError("mesh is not a closed, consistently oriented manifold")
+    return a0, float(A0[0]), float(V0[0])
 
 
 def mesh_edges(tris, x_ref):
@@ -218,6 +256,12 @@ class OracleSim:
         m = lib().oracle_mesh_add(self._h, int(tmpl), _p(x), float(ks), float(kb))
         self._mesh_nn.append(x.shape[0])
         return m
+
+    def set_membrane(self, mesh, kbtp=0.0, kg=0.0, kl=0.0, kv=0.0):
+        """Adds the rest of the paper's membrane energy to a mesh: WLC-POW
+        stretching, area and volume constraints (zero: term absent)."""
+        if lib().oracle_mesh_membrane(self._h, int(mesh), float(kbtp), float(kg), float(kl), float(kv)) != 0:
+            raise ValueError("unknown mesh")
 
     def step(self, n=1):
         if lib().oracle_sim_step(self._h, int(n)) != 0:

@@ -14,7 +14,10 @@
  *             Eq. (1) evolution, Eq. (2) equilibrium, Eq. (3) moments with the
  *             half-force shift, Eq. (5) tau-viscosity relation.
  *   Sec. 2.2  membrane forces: linear springs 1/2 ks (l - l0)^2 per edge and the
- *             dihedral bending energy of Eq. (8), F = -dE/dX.
+ *             dihedral bending energy of Eq. (8), F = -dE/dX; optionally the
+ *             rest of the paper's membrane energy, Eq. (6): the WLC-POW
+ *             stretching energy of Eq. (7), the global and local area
+ *             constraints of Eq. (9) and the volume constraint of Eq. (10).
  *   Sec. 2.3  Eq. (14) velocity interpolation, Eq. (15) force spreading, with
  *             the cosine kernel of Eq. (16) or Peskin's 4-point kernel.
  *
@@ -96,6 +99,8 @@ typedef struct {
                     v3 opposite in the triangle holding v2->v1 */
   double *l0;    /* [ne] rest length */
   double *th0;   /* [ne] rest bending angle */
+  double *a0;    /* [nt] rest triangle area (A_j0 of Eq. (9)) */
+  double A0, V0; /* rest total area and enclosed volume (Eqs. (9), (10)) */
 } otmpl;
 
 static void cross3(const double *a, const double *b, double *c) {
@@ -153,6 +158,7 @@ static int tmpl_build(otmpl *T, int nn, int nt, const int *tri) {
   if (ok != 0) return -1;
   T->l0 = (double *)calloc((size_t)T->ne, sizeof(double));
   T->th0 = (double *)calloc((size_t)T->ne, sizeof(double));
+  T->a0 = (double *)calloc((size_t)T->nt, sizeof(double));
   return 0;
 }
 
@@ -189,6 +195,9 @@ static double dihedral_angle(const double *v0, const double *v1, const double *v
 /*   dtheta/dv2 = -t0 dtheta/dv0 - t3 dtheta/dv3,                             */
 /* where t0 = (v0 - v1).e / L^2 and t3 = (v3 - v1).e / L^2.                   */
 /* ------------------------------------------------------------------------ */
+static double tri_area(const double *p1, const double *p2, const double *p3);
+static double tri_volume(const double *p1, const double *p2, const double *p3, const double *c);
+
 static void tmpl_rest(otmpl *T, const double *xr) {
   for (int j = 0; j < T->ne; ++j) {
     const int *e = T->ev + 4 * j;
@@ -197,6 +206,14 @@ static void tmpl_rest(otmpl *T, const double *xr) {
     double d[3] = {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]};
     T->l0[j] = sqrt(dot3(d, d));
     T->th0[j] = dihedral_angle(v0, v1, v2, v3);
+  }
+  T->A0 = 0.0;
+  T->V0 = 0.0;
+  for (int t = 0; t < T->nt; ++t) {
+    const int *q = T->tri + 3 * t;
+    T->a0[t] = tri_area(xr + 3 * q[0], xr + 3 * q[1], xr + 3 * q[2]);
+    T->A0 += T->a0[t];
+    T->V0 += tri_volume(xr + 3 * q[0], xr + 3 * q[1], xr + 3 * q[2], xr);
   }
 }
 
@@ -251,8 +268,114 @@ static double membrane_force(const otmpl *T, const double *x, double ks, double 
   return E;
 }
 
+/* ------------------------------------------------------------------------ */
+/* The rest of the membrane energy of Eq. (6), Sec. 2.2.                     */
+/*                                                                            */
+/* Stretching, Eq. (7), per edge with x = l / l_m, l_m = 2 l0 (the maximum     */
+/* bond length is twice the equilibrium one), C = kBT / p:                    */
+/*   U = C l_m / 4 (3 x^2 - 2 x^3) / (1 - x) + k_p / l,                       */
+/*   dU/dl = C (1 / (4 (1 - x)^2) - 1/4 + x) - k_p / l^2.                     */
+/* k_p makes each bond force-free at its rest length (x = 1/2), the paper's   */
+/* rule for fixing it: C (1 - 1/4 + 1/2) = k_p / l0^2, k_p = 5/4 C l0^2.       */
+/*                                                                            */
+/* Area, Eq. (9): U = kg (A - A0)^2 / (2 A0) + sum_j kl (A_j - A_j0)^2 /      */
+/* (2 A_j0), A_j = |(p2 - p1) x (p3 - p1)| / 2, A = sum_j A_j; with n the      */
+/* unit normal of a counter-clockwise triangle, dA_j/dp1 = n x (p3 - p2) / 2   */
+/* and cyclically.                                                            */
+/*                                                                            */
+/* Volume, Eq. (10): U = kv (V - V0)^2 / (2 V0), V = sum_j (p1 - c) .          */
+/* ((p2 - c) x (p3 - c)) / 6 over the outward triangles, for any fixed point   */
+/* c (the closed surface makes the sum independent of it; c = the mesh's       */
+/* first node keeps the terms small); dV/dp1 = (p2 - c) x (p3 - c) / 6 and     */
+/* cyclically.                                                                */
+/* ------------------------------------------------------------------------ */
+static double tri_area(const double *p1, const double *p2, const double *p3) {
+  double a[3], b[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = p2[k] - p1[k];
+    b[k] = p3[k] - p1[k];
+  }
+  cross3(a, b, n);
+  return 0.5 * sqrt(dot3(n, n));
+}
+
+static double tri_volume(const double *p1, const double *p2, const double *p3, const double *c) {
+  double a[3], b[3], d[3], n[3];
+  for (int k = 0; k < 3; ++k) {
+    a[k] = p1[k] - c[k];
+    b[k] = p2[k] - c[k];
+    d[k] = p3[k] - c[k];
+  }
+  cross3(b, d, n);
+  return dot3(a, n) / 6.0;
+}
+
+/* Adds the force of the terms above to F; returns their energy.  A bond at or
+ * beyond its maximum length has no finite energy: returns NAN. */
+static double membrane_extra(const otmpl *T, const double *x, double kbtp, double kg, double kl,
+                             double kv, double *F) {
+  double E = 0.0;
+  if (kbtp != 0.0) {
+    for (int j = 0; j < T->ne; ++j) {
+      const int *ev = T->ev + 4 * j;
+      const double *v1 = x + 3 * ev[1], *v2 = x + 3 * ev[2];
+      double d[3] = {v2[0] - v1[0], v2[1] - v1[1], v2[2] - v1[2]};
+      double l = sqrt(dot3(d, d));
+      double lm = 2.0 * T->l0[j];
+      double xr = l / lm;
+      if (!(xr < 1.0)) return NAN;
+      double kp = 1.25 * kbtp * T->l0[j] * T->l0[j];
+      E += kbtp * lm / 4.0 * (3.0 * xr * xr - 2.0 * xr * xr * xr) / (1.0 - xr) + kp / l;
+      double dUdl = kbtp * (1.0 / (4.0 * (1.0 - xr) * (1.0 - xr)) - 0.25 + xr) - kp / (l * l);
+      for (int k = 0; k < 3; ++k) {
+        double fk = dUdl * d[k] / l;  /* dU/dv2; the force on v2 is minus that */
+        F[3 * ev[1] + k] += fk;
+        F[3 * ev[2] + k] -= fk;
+      }
+    }
+  }
+  if (kg != 0.0 || kl != 0.0 || kv != 0.0) {
+    double A = 0.0, V = 0.0;
+    for (int t = 0; t < T->nt; ++t) {
+      const int *q = T->tri + 3 * t;
+      A += tri_area(x + 3 * q[0], x + 3 * q[1], x + 3 * q[2]);
+      V += tri_volume(x + 3 * q[0], x + 3 * q[1], x + 3 * q[2], x);
+    }
+    E += kg * (A - T->A0) * (A - T->A0) / (2.0 * T->A0) + kv * (V - T->V0) * (V - T->V0) / (2.0 * T->V0);
+    double cg = kg * (A - T->A0) / T->A0, cv = kv * (V - T->V0) / T->V0;
+    for (int t = 0; t < T->nt; ++t) {
+      const int *q = T->tri + 3 * t;
+      const double *p[3] = {x + 3 * q[0], x + 3 * q[1], x + 3 * q[2]};
+      double At = tri_area(p[0], p[1], p[2]);
+      E += kl * (At - T->a0[t]) * (At - T->a0[t]) / (2.0 * T->a0[t]);
+      double ca = cg + kl * (At - T->a0[t]) / T->a0[t];
+      double a[3], b[3], nrm[3];
+      for (int k = 0; k < 3; ++k) {
+        a[k] = p[1][k] - p[0][k];
+        b[k] = p[2][k] - p[0][k];
+      }
+      cross3(a, b, nrm);
+      double nl = sqrt(dot3(nrm, nrm));
+      for (int k = 0; k < 3; ++k) nrm[k] /= nl;
+      for (int i = 0; i < 3; ++i) {
+        const double *pn = p[(i + 1) % 3], *pp = p[(i + 2) % 3];
+        double opp[3] = {pp[0] - pn[0], pp[1] - pn[1], pp[2] - pn[2]}, gA[3];
+        cross3(nrm, opp, gA);  /* 2 dA_t/dp_i */
+        double r1[3], r2[3], gV[3];
+        for (int k = 0; k < 3; ++k) {
+          r1[k] = pn[k] - x[k];
+          r2[k] = pp[k] - x[k];
+        }
+        cross3(r1, r2, gV);  /* 6 dV_t/dp_i */
+        for (int k = 0; k < 3; ++k) F[3 * q[i] + k] -= ca * 0.5 * gA[k] + cv * gV[k] / 6.0;
+      }
+    }
+  }
+  return E;
+}
+
 static void tmpl_free(otmpl *T) {
-  free(T->tri); free(T->ev); free(T->l0); free(T->th0);
+  free(T->tri); free(T->ev); free(T->l0); free(T->th0); free(T->a0);
   memset(T, 0, sizeof(*T));
 }
 
@@ -270,6 +393,39 @@ int oracle_membrane(int nn, int nt, const int *tri, const double *xref, const do
   int ne = T.ne;
   tmpl_free(&T);
   return ne;
+}
+
+/* The same with the rest of Eq. (6): WLC-POW stretching (kbtp = kBT / p),
+ * global / local area (kg, kl) and volume (kv) constraints.  Returns #edges,
+ * -1 on a bad mesh, -2 where a bond reaches its maximum length. */
+int oracle_membrane_full(int nn, int nt, const int *tri, const double *xref, const double *x,
+                         double ks, double kb, double kbtp, double kg, double kl, double kv,
+                         double *F, double *E) {
+  otmpl T;
+  memset(&T, 0, sizeof(T));
+  if (tmpl_build(&T, nn, nt, tri) != 0) { tmpl_free(&T); return -1; }
+  tmpl_rest(&T, xref);
+  memset(F, 0, sizeof(double) * 3 * (size_t)nn);
+  double e = membrane_force(&T, x, ks, kb, F);
+  double e2 = membrane_extra(&T, x, kbtp, kg, kl, kv, F);
+  if (E) *E = e + e2;
+  int ne = T.ne;
+  tmpl_free(&T);
+  return isnan(e2) ? -2 : ne;
+}
+
+/* Rest area, per-triangle rest areas and rest volume of a template (tests). */
+int oracle_template_rest(int nn, int nt, const int *tri, const double *xref, double *a0,
+                         double *A0, double *V0) {
+  otmpl T;
+  memset(&T, 0, sizeof(T));
+  if (tmpl_build(&T, nn, nt, tri) != 0) { tmpl_free(&T); return -1; }
+  tmpl_rest(&T, xref);
+  if (a0) memcpy(a0, T.a0, sizeof(double) * (size_t)nt);
+  *A0 = T.A0;
+  *V0 = T.V0;
+  tmpl_free(&T);
+  return 0;
 }
 
 /* Edge list and rest data (v0,v1,v2,v3 per edge, l0, theta0) for tests. */
@@ -422,7 +578,7 @@ int oracle_interp_field(const int n[3], const int wall[3], const double *ulo, co
 /* ------------------------------------------------------------------------ */
 /* The coupled simulation.                                                   */
 /* ------------------------------------------------------------------------ */
-typedef struct { int tmpl, off, nn; double ks, kb; } omesh;
+typedef struct { int tmpl, off, nn; double ks, kb, kbtp, kg, kl, kv; } omesh;
 
 typedef struct osim {
   ogeom G;
@@ -514,6 +670,7 @@ int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
   S->me = (omesh *)realloc(S->me, sizeof(omesh) * (size_t)(S->nme + 1));
   omesh *M = &S->me[S->nme];
   M->tmpl = tmpl; M->off = S->nnode; M->nn = nn; M->ks = ks; M->kb = kb;
+  M->kbtp = M->kg = M->kl = M->kv = 0.0;
   S->X = (double *)realloc(S->X, sizeof(double) * 3 * (size_t)(S->nnode + nn));
   S->F = (double *)realloc(S->F, sizeof(double) * 3 * (size_t)(S->nnode + nn));
   S->U = (double *)realloc(S->U, sizeof(double) * 3 * (size_t)(S->nnode + nn));
@@ -523,6 +680,15 @@ int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
   S->nnode += nn;
   S->obs_valid = 0;
   return S->nme++;
+}
+
+/* The rest of the paper's membrane energy on one mesh (zero: absent). */
+int oracle_mesh_membrane(osim *S, int mesh, double kbtp, double kg, double kl, double kv) {
+  if (mesh < 0 || mesh >= S->nme) return -1;
+  omesh *M = &S->me[mesh];
+  M->kbtp = kbtp; M->kg = kg; M->kl = kl; M->kv = kv;
+  S->obs_valid = 0;
+  return 0;
 }
 
 /* Steps 1-4 of a timestep at the current state (no mutation of f or X):
@@ -535,6 +701,9 @@ static int observe(osim *S) {
   for (int m = 0; m < S->nme; ++m) {
     const omesh *M = &S->me[m];
     membrane_force(&S->tm[M->tmpl], S->X + 3 * (size_t)M->off, M->ks, M->kb, S->F + 3 * (size_t)M->off);
+    if (isnan(membrane_extra(&S->tm[M->tmpl], S->X + 3 * (size_t)M->off, M->kbtp, M->kg, M->kl, M->kv,
+                             S->F + 3 * (size_t)M->off)))
+      return -1;
   }
   memset(S->g, 0, sizeof(double) * 3 * (size_t)nc);
   if (spread(&S->G, S->kind, S->nnode, S->X, S->F, S->g) != 0) return -1;
