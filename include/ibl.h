@@ -152,6 +152,22 @@ ibl_status ibl_template_add(ibl_sim sim, int32_t n_nodes, int32_t n_tris, const 
 ibl_status ibl_mesh_add(ibl_sim sim, int32_t template_id, const double* x, double ks, double kb,
                         int32_t* out_mesh);
 
+/* Add the rest of the paper's membrane energy, Eq. (6), to a capsule (all
+ * zero after ibl_mesh_add; zero: term absent).  They add to the springs and
+ * bending of ibl_mesh_add (pass ks = 0 there for the paper's model):
+ *   kbt_p  WLC-POW stretching, Eq. (7), C = kBT / p: maximum bond length
+ *          l_m = 2 l0, and the repulsive constant k_p = 5/4 C l0^2 that makes
+ *          every bond force-free at its rest length l0;
+ *   kg, kl global and local area constraints, Eq. (9), rest areas from x_ref;
+ *   kv     volume constraint, Eq. (10), rest volume enclosed by x_ref.
+ * A bond at or beyond l_m sets IBL_HEALTH_FORCE_RANGE and adds no force.
+ * Set the terms before ibl_batch_create on a batch holding the simulation.
+ * Errors: IBL_ERR_ARG (unknown mesh, a negative or non-finite constant, a
+ * reference shape with a degenerate triangle or no enclosed volume for a term
+ * that needs it), IBL_ERR_UNSUPPORTED (template beyond the LDS force kernel,
+ * more than 642 nodes or 1920 edges). */
+ibl_status ibl_mesh_membrane(ibl_sim sim, int32_t mesh, double kbt_p, double kg, double kl, double kv);
+
 /* Advance n_steps coupled timesteps, asynchronously on the simulation's
  * stream (replayed HIP graphs).  State afterwards: (f^N, X^N). */
 ibl_status ibl_step(ibl_sim sim, int64_t n_steps);

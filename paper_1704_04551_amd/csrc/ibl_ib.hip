@@ -404,6 +404,21 @@ __device__ __forceinline__ void gather_node(const SimDev& S, const R (*pe)[kLdsE
   }
 }
 
+// Force of a mesh's WLC-POW, area and volume terms (written by k_membrane at
+// the same positions), added to a node's spring and bending force.
+__device__ __forceinline__ bool mesh_has_terms(const SimDev& S, int m) {
+  const GLB double* mm = S.mesh_mem + 4 * (int64_t)m;
+  return mm[0] != 0.0 || mm[1] != 0.0 || mm[2] != 0.0 || mm[3] != 0.0;
+}
+
+__device__ __forceinline__ void add_membrane_terms(const SimDev& S, const Items& it, int m, bool act, int gid,
+                                                   double F[3]) {
+  if (!it.membrane || !act || !mesh_has_terms(S, m)) return;
+  const int64_t ms = (int64_t)S.maxn;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) F[a] += S.Fext[a * ms + gid];
+}
+
 template <typename R>
 __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev* __restrict__ sims,
                                                                     Items it, int mode) {
@@ -448,6 +463,8 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
     double Fa[3], Fb[3];
     gather_node<R>(S, pe, acta ? S.inc_ptr[row0 + ia] : 0, acta ? S.inc_ptr[row0 + ia + 1] : 0, e0, Fa);
     gather_node<R>(S, pe, actb ? S.inc_ptr[row0 + ib] : 0, actb ? S.inc_ptr[row0 + ib + 1] : 0, e0, Fb);
+    add_membrane_terms(S, it, m, acta, off + ia, Fa);
+    add_membrane_terms(S, it, m, actb, off + ib, Fb);
     const double Xa[3] = {acta ? X0[ia] : 0.0, acta ? X0[ms + ia] : 0.0, acta ? X0[2 * ms + ia] : 0.0};
     const double Xb[3] = {actb ? X0[ib] : 0.0, actb ? X0[ms + ib] : 0.0, actb ? X0[2 * ms + ib] : 0.0};
     uint32_t fbits = 0u;
@@ -554,6 +571,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
           F[a] = act ? (double)acc[a][i] * 0x1p-40 : 0.0;
           Xp[a] = act ? X0[a * ms + i] : 0.0;
         }
+        add_membrane_terms(S, it, m, act, off + i, F);
         emit_nodes<float>(S, bt, L, act, off + i, Xp, F, mode, fbits);
       }
     } else {
@@ -564,11 +582,152 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
           F[a] = (double)acc[a][i] * 0x1p-40;
           Xp[a] = X0[a * ms + i];
         }
+        add_membrane_terms(S, it, m, true, off + i, F);
         emit_node<float>(S, L, off + i, Xp, F, mode, fbits);
       }
     }
     flush_fmax(S, L.par, &wmax, fbits);  // (its barrier: accumulators read before the next
                                          // capsule clears them)
+  }
+}
+
+// ------------------------------------------- membrane area, volume, WLC-POW --
+// The rest of the membrane energy of Eq. (6), per capsule (one workgroup):
+//  * WLC-POW stretching, Eq. (7), per edge: x = l / l_m with l_m = 2 l0 (the
+//    maximum bond length is twice the rest length), C = kBT / p,
+//    dU/dl = C (1 / (4 (1 - x)^2) - 1/4 + x) - k_p / l^2, and k_p = 5/4 C l0^2
+//    so that every bond is force-free at its rest length (x = 1/2);
+//  * area, Eq. (9): the global term kg (A - A0) / A0 and each triangle's local
+//    term kl (A_j - A_j0) / A_j0 multiply dA_j/dp = n x (opposite edge) / 2;
+//  * volume, Eq. (10): kv (V - V0) / V0 multiplies dV_j/dp = (q - c) x (r - c)
+//    / 6, with V = sum_j (p - c) . ((q - c) x (r - c)) / 6 over the outward
+//    triangles about c = the mesh's first node (any fixed point gives the same
+//    V on a closed surface; a point on the mesh keeps the terms small).
+// A and V are summed per thread in triangle order, then over the workgroup in
+// a fixed tree, so they are reproducible.  The node forces are summed in LDS
+// as 64-bit fixed-point integers (order-independent; the two shares of a bond
+// are exact negatives) and written to Fext, which the force kernels add to the
+// spring and bending force.  These shares are bounded by bond lengths and the
+// capsule's size (no 1 / area factor as in bending), so the scale is finer
+// than k_forces_fx's: units of 2^-46, a share component limited to 32 lattice
+// units (health bit beyond), one rounding of at most 2^-47 = 7.1e-15 per
+// share, well inside FP64 parity.  A bond at or beyond its maximum length has
+// no finite energy: it sets the force-range health bit and contributes nothing.
+constexpr int kMemThreads = 256;
+constexpr double kMemLimit = 32.0;  // |share component| limit: 2^5 = 2^(51 - 46)
+
+__device__ __forceinline__ long long mem_quant(const SimDev& S, double v) {
+  if (!(fabs(v) < kMemLimit)) {
+    atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
+    v = isnan(v) ? 0.0 : copysign(kMemLimit, v);
+  }
+  // |v 2^46| < 2^51: v 2^46 + 1.5 2^52 rounds to an integer of [2^52, 2^53)
+  return __double_as_longlong(fma(v, 0x1p46, 0x1.8p52)) - __double_as_longlong(0x1.8p52);
+}
+
+__global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ long long acc[3][kLdsNodes];
+  __shared__ double red[2][kMemThreads];
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    const int m = item - it.mesh_off[s];
+    if (!mesh_has_terms(S, m)) continue;  // uniform
+    const GLB double* mm = S.mesh_mem + 4 * (int64_t)m;
+    const double kbtp = mm[0], kg = mm[1], kl = mm[2], kv = mm[3];
+    const int tm = S.mesh_tmpl[m];
+    const int off = S.mesh_off[m];
+    const int nn = S.t_nn[tm], ne = S.t_ne[tm], nt = S.t_nt[tm];
+    const int e0 = S.t_edge0[tm], tr0 = S.t_tri0[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const GLB double* X0 = S.X + off;
+    for (int i = tid; i < nn; i += kMemThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
+    const bool surf = kg != 0.0 || kl != 0.0 || kv != 0.0;
+    const D3 c = {X0[0], X0[ms], X0[2 * ms]};
+    double cg = 0.0, cv = 0.0;
+    if (surf) {  // uniform
+      double As = 0.0, Vs = 0.0;
+      for (int t = tid; t < nt; t += kMemThreads) {
+        const GLB int* q = S.ttri + 3 * (int64_t)(tr0 + t);
+        D3 p[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) p[k] = {X0[q[k]] - c.x, X0[ms + q[k]] - c.y, X0[2 * ms + q[k]] - c.z};
+        const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
+        As += 0.5 * sqrt(dot(n, n));
+        Vs += dot(p[0], cross(p[1], p[2])) / 6.0;
+      }
+      red[0][tid] = As;
+      red[1][tid] = Vs;
+      __syncthreads();
+      for (int w = kMemThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) {
+          red[0][tid] += red[0][tid + w];
+          red[1][tid] += red[1][tid + w];
+        }
+        __syncthreads();
+      }
+      const double A0 = S.tav0[2 * tm], V0 = S.tav0[2 * tm + 1];
+      cg = kg * (red[0][0] - A0) / A0;
+      cv = kv * (red[1][0] - V0) / V0;
+    }
+    __syncthreads();  // accumulators cleared, sums read
+    if (surf) {  // uniform
+      for (int t = tid; t < nt; t += kMemThreads) {
+        const GLB int* q = S.ttri + 3 * (int64_t)(tr0 + t);
+        int v[3];
+        D3 p[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          v[k] = q[k];
+          p[k] = {X0[v[k]] - c.x, X0[ms + v[k]] - c.y, X0[2 * ms + v[k]] - c.z};
+        }
+        const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
+        const double nl = sqrt(dot(n, n));
+        const double a0 = S.ta0[tr0 + t];
+        const double ca = cg + kl * (0.5 * nl - a0) / a0;
+        const D3 nh = {n.x / nl, n.y / nl, n.z / nl};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const D3 pn = p[(k + 1) % 3], pp = p[(k + 2) % 3];
+          const D3 gA = cross(nh, sub(pp, pn));  // 2 dA_j/dp
+          const D3 gV = cross(pn, pp);           // 6 dV_j/dp
+          const double f[3] = {-(ca * 0.5 * gA.x + cv * gV.x / 6.0), -(ca * 0.5 * gA.y + cv * gV.y / 6.0),
+                               -(ca * 0.5 * gA.z + cv * gV.z / 6.0)};
+#pragma unroll
+          for (int a = 0; a < 3; ++a) fx_add(&acc[a][v[k]], mem_quant(S, f[a]));
+        }
+      }
+    }
+    if (kbtp != 0.0) {  // uniform
+      for (int e = tid; e < ne; e += kMemThreads) {
+        const GLB int* ev = S.ev + 4 * (e0 + e);
+        const int v1 = ev[1], v2 = ev[2];
+        const D3 d = {X0[v2] - X0[v1], X0[ms + v2] - X0[ms + v1], X0[2 * ms + v2] - X0[2 * ms + v1]};
+        const double l = sqrt(dot(d, d)), l0 = S.el0[e0 + e];
+        const double x = l / (2.0 * l0);
+        if (!(x < 1.0)) {
+          atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
+          continue;
+        }
+        const double kp = 1.25 * kbtp * l0 * l0;
+        const double dUdl = kbtp * (1.0 / (4.0 * (1.0 - x) * (1.0 - x)) - 0.25 + x) - kp / (l * l);
+        const double f[3] = {dUdl * d.x / l, dUdl * d.y / l, dUdl * d.z / l};  // force on v1
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const long long qf = mem_quant(S, f[a]);
+          fx_add(&acc[a][v1], qf);
+          fx_add(&acc[a][v2], -qf);
+        }
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < nn; i += kMemThreads) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) S.Fext[a * ms + off + i] = (double)acc[a][i] * 0x1p-46;
+    }
+    __syncthreads();  // accumulators read before the next capsule clears them
   }
 }
 
@@ -658,6 +817,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
         }
       }
       const int gid = off + i;
+      add_membrane_terms(S, it, m, act, gid, F);
       const double Xp[3] = {act ? S.X[gid] : 0.0, act ? S.X[ms + gid] : 0.0, act ? S.X[2 * ms + gid] : 0.0};
       if (S.skin == 0) emit_nodes<R>(S, bt, L, act, gid, Xp, F, mode, fbits);  // uniform
       else if (act) emit_node<R>(S, L, gid, Xp, F, mode, fbits);
@@ -851,6 +1011,9 @@ int grid_for(int items, int cap) {
 template <typename R>
 void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
   if (it.mesh_total <= 0) return;
+  if (it.membrane)
+    hipLaunchKernelGGL(k_membrane, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kMemThreads), 0, s, sims, it,
+                       mode);
   if (it.big_templates || it.forces_variant == 1) {
     hipLaunchKernelGGL(k_edge_forces, dim3(grid_for(it.mesh_total * kEdgeChunks, 1 << 20)), dim3(256), 0, s,
                        sims, it, mode);

@@ -141,6 +141,8 @@ struct SimDev {
   IBL_G(int32_t) mesh_off;      // [max_meshes] first global node
   IBL_G(double) mesh_ks;
   IBL_G(double) mesh_kb;
+  IBL_G(double) mesh_mem;       // [max_meshes][4] kBT/p, kg, kl, kv (zero: term absent)
+  IBL_G(double) Fext;           // [3][max_nodes] force of those terms (k_membrane)
   // templates
   IBL_G(int32_t) t_nn;          // [max_templates]
   IBL_G(int32_t) t_node0;       // first template-node index
@@ -152,6 +154,11 @@ struct SimDev {
   IBL_G(double) el0;            // [max_template_edges] rest length
   IBL_G(double) ec0;            // cos(theta0)
   IBL_G(double) es0;            // sin(theta0)
+  IBL_G(int32_t) t_nt;          // [max_templates] triangles
+  IBL_G(int32_t) t_tri0;        // first template-triangle index
+  IBL_G(int32_t) ttri;          // [max_template_edges][3] outward triangles, template-local nodes
+  IBL_G(double) ta0;            // [max_template_edges] rest triangle area
+  IBL_G(double) tav0;           // [max_templates][2] rest area, rest enclosed volume
   // control
   IBL_G(int64_t) step;          // completed steps (A/B parity = step & 1)
   IBL_G(int64_t) remaining;     // steps still to run in the current launch sequence
@@ -170,6 +177,7 @@ struct Items {
   int32_t big_templates;     // 1 when a template exceeds the LDS force kernel
   int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels,
                              // 2: FP32 / FP16 storage through the edge-share LDS kernel
+  int32_t membrane;          // 1 when some mesh has WLC-POW, area or volume terms
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;

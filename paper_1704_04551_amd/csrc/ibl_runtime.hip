@@ -12,6 +12,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -79,8 +80,9 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 struct Layout {
   size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, blist, bb0, fmax, lctl, hcount, hlist;
-  size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb;
+  size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb, mesh_mem, fext;
   size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0, txref;
+  size_t t_nt, t_tri0, ttri, ta0, tav0;
   size_t step, remaining, health, red, red_out, simdev, items;
   size_t total;
   int64_t ncell, nbrick, ncube, nred;
@@ -160,6 +162,8 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.mesh_off = take((size_t)d->max_meshes * 4);
   L.mesh_ks = take((size_t)d->max_meshes * 8);
   L.mesh_kb = take((size_t)d->max_meshes * 8);
+  L.mesh_mem = take((size_t)d->max_meshes * 4 * 8);
+  L.fext = take(3 * maxn * 8);
   L.t_nn = take((size_t)d->max_templates * 4);
   L.t_node0 = take((size_t)d->max_templates * 4);
   L.t_edge0 = take((size_t)d->max_templates * 4);
@@ -171,6 +175,11 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.ec0 = take((size_t)d->max_template_edges * 8);
   L.es0 = take((size_t)d->max_template_edges * 8);
   L.txref = take((size_t)d->max_template_nodes * 3 * 8);  // staging of a template's reference shape
+  L.t_nt = take((size_t)d->max_templates * 4);
+  L.t_tri0 = take((size_t)d->max_templates * 4);
+  L.ttri = take((size_t)d->max_template_edges * 3 * 4);  // a closed surface has fewer triangles than edges
+  L.ta0 = take((size_t)d->max_template_edges * 8);
+  L.tav0 = take((size_t)d->max_templates * 2 * 8);
   L.step = take(8);
   L.remaining = take(8);
   L.health = take(4);
@@ -196,8 +205,10 @@ struct ibl_sim_s {
   int32_t* ditems = nullptr; // [10] prefix tables (in the arena)
   Items items;
   // templates
-  int ntmpl = 0, tnodes = 0, tedges = 0;
+  int ntmpl = 0, tnodes = 0, tedges = 0, ttris = 0;
   std::vector<int> t_nn, t_node0, t_edge0;
+  std::vector<char> t_big;  // per template: beyond the LDS force kernel
+  std::vector<std::array<double, 3>> t_rest;  // per template: smallest rest triangle area, A0, V0
   int inc_total = 0;
   int big_templates = 0;
   // per template: internal node i holds the caller's node perm[i] (spatial
@@ -206,6 +217,7 @@ struct ibl_sim_s {
   // meshes
   int nmesh = 0, nnodes = 0;
   std::vector<int> mesh_tmpl, mesh_off;
+  int membrane = 0;  // some mesh has WLC-POW, area or volume terms
   // graphs (invalidated when the work lists change)
   hipGraphExec_t g1 = nullptr, gN = nullptr;
 };
@@ -306,6 +318,7 @@ ibl_status upload_simdev(ibl_sim S) {
   it.cube_off = S->ditems + 6;
   it.big_templates = S->big_templates;
   it.forces_variant = forces_variant();
+  it.membrane = S->membrane;
   it.sub = 0;
   drop_graphs(S->g1, S->gN);
   return IBL_OK;
@@ -417,6 +430,13 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.mesh_off = (int32_t*)(A + L.mesh_off);
   d.mesh_ks = (double*)(A + L.mesh_ks);
   d.mesh_kb = (double*)(A + L.mesh_kb);
+  d.mesh_mem = (double*)(A + L.mesh_mem);
+  d.Fext = (double*)(A + L.fext);
+  d.t_nt = (int32_t*)(A + L.t_nt);
+  d.t_tri0 = (int32_t*)(A + L.t_tri0);
+  d.ttri = (int32_t*)(A + L.ttri);
+  d.ta0 = (double*)(A + L.ta0);
+  d.tav0 = (double*)(A + L.tav0);
   d.t_nn = (int32_t*)(A + L.t_nn);
   d.t_node0 = (int32_t*)(A + L.t_node0);
   d.t_edge0 = (int32_t*)(A + L.t_edge0);
@@ -525,7 +545,7 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   const int ne = (int)(ev.size() / 4);
   if (ne > 3 * nn) return fail(IBL_ERR_UNSUPPORTED, "more than 3 edges per node (surface of genus > 1)");
   if (S->ntmpl + 1 > S->desc.max_templates || S->tnodes + nn > S->desc.max_template_nodes ||
-      S->tedges + ne > S->desc.max_template_edges)
+      S->tedges + ne > S->desc.max_template_edges || S->ttris + nt > S->desc.max_template_edges)
     return fail(IBL_ERR_NOMEM, "template capacity exceeded");
   HIPCHK(hipSetDevice(S->device));
   const int e0 = S->tedges, n0 = S->tnodes;
@@ -555,6 +575,35 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
     for (int a = 0; a < 3; ++a) xr_int[3 * (size_t)i + a] = xref[3 * (size_t)perm[i] + a];
   if (!e) e = hipMemcpyAsync(dx, xr_int.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice, S->stream);
   if (!e) e = launch_template_rest(S->dd, S->ntmpl, ne, dx, S->stream);
+  // triangles (internal numbering) with their rest areas, and the rest area and
+  // enclosed volume of Eqs. (9) and (10), the volume taken about internal node 0
+  // as the membrane kernel does
+  const int tr0 = S->ttris;
+  std::vector<int> ttri(3 * (size_t)nt);
+  std::vector<double> ta0(nt);
+  double av0[2] = {0.0, 0.0}, amin = 1e300;
+  const double* c0 = xr_int.data();
+  for (int t = 0; t < nt; ++t) {
+    double p[3][3];
+    for (int k = 0; k < 3; ++k) {
+      ttri[3 * (size_t)t + k] = inv[tris[3 * t + k]];
+      for (int a = 0; a < 3; ++a) p[k][a] = xref[3 * (size_t)tris[3 * t + k] + a] - c0[a];
+    }
+    const double u[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+    const double w[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+    const double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    ta0[t] = 0.5 * sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    const double qr[3] = {p[1][1] * p[2][2] - p[1][2] * p[2][1], p[1][2] * p[2][0] - p[1][0] * p[2][2],
+                          p[1][0] * p[2][1] - p[1][1] * p[2][0]};
+    av0[0] += ta0[t];
+    av0[1] += (p[0][0] * qr[0] + p[0][1] * qr[1] + p[0][2] * qr[2]) / 6.0;
+    amin = fmin(amin, ta0[t]);
+  }
+  if (!e) e = hipMemcpyAsync(d.ttri + 3 * (size_t)tr0, ttri.data(), ttri.size() * 4, hipMemcpyHostToDevice, S->stream);
+  if (!e) e = hipMemcpyAsync(d.ta0 + tr0, ta0.data(), ta0.size() * 8, hipMemcpyHostToDevice, S->stream);
+  if (!e) e = hipMemcpyAsync(d.tav0 + 2 * (size_t)S->ntmpl, av0, 16, hipMemcpyHostToDevice, S->stream);
+  if (!e) e = hipMemcpyAsync(d.t_nt + S->ntmpl, &nt, 4, hipMemcpyHostToDevice, S->stream);
+  if (!e) e = hipMemcpyAsync(d.t_tri0 + S->ntmpl, &tr0, 4, hipMemcpyHostToDevice, S->stream);
   if (!e) e = hipStreamSynchronize(S->stream);
   if (e) return fail(IBL_ERR_DEVICE, std::string("template upload: ") + hipGetErrorString(e));
   S->t_nn.push_back(nn);
@@ -562,8 +611,11 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   S->t_node0.push_back(n0);
   S->t_edge0.push_back(e0);
   if (nn > kLdsNodes || ne > kLdsEdges) S->big_templates = 1;
+  S->t_big.push_back(nn > kLdsNodes || ne > kLdsEdges ? 1 : 0);
+  S->t_rest.push_back({amin, av0[0], av0[1]});
   S->tnodes += nn;
   S->tedges += ne;
+  S->ttris += nt;
   S->inc_total += (int)inc.size();
   *out_template = S->ntmpl++;
   return IBL_OK;
@@ -601,12 +653,33 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
   HIPCHK(hipMemcpyAsync(d.mesh_off + S->nmesh, &off, 4, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_ks + S->nmesh, &ks, 8, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_kb + S->nmesh, &kb, 8, hipMemcpyHostToDevice, S->stream));
+  const double no_terms[4] = {0.0, 0.0, 0.0, 0.0};
+  HIPCHK(hipMemcpyAsync(d.mesh_mem + 4 * (size_t)S->nmesh, no_terms, 32, hipMemcpyHostToDevice, S->stream));
   HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // new nodes: rebuild at the next step
   HIPCHK(hipStreamSynchronize(S->stream));
   S->mesh_tmpl.push_back(tmpl);
   S->mesh_off.push_back(off);
   S->nnodes += nn;
   *out_mesh = S->nmesh++;
+  return upload_simdev(S);
+}
+
+ibl_status ibl_mesh_membrane(ibl_sim S, int32_t mesh, double kbt_p, double kg, double kl, double kv) {
+  if (!S) return fail(IBL_ERR_ARG, "null simulation");
+  if (mesh < 0 || mesh >= S->nmesh) return fail(IBL_ERR_ARG, "unknown mesh");
+  const double k[4] = {kbt_p, kg, kl, kv};
+  for (double v : k)
+    if (!isfinite(v) || v < 0.0) return fail(IBL_ERR_ARG, "membrane constants must be finite and >= 0");
+  const int tm = S->mesh_tmpl[mesh];
+  if (S->t_big[tm])
+    return fail(IBL_ERR_UNSUPPORTED, "area, volume and WLC-POW terms need a template within the LDS force kernel");
+  if ((kl != 0.0 && !(S->t_rest[tm][0] > 0.0)) || (kg != 0.0 && !(S->t_rest[tm][1] > 0.0)) ||
+      (kv != 0.0 && !(S->t_rest[tm][2] > 0.0)))
+    return fail(IBL_ERR_ARG, "reference shape with a degenerate triangle or no enclosed volume");
+  HIPCHK(hipSetDevice(S->device));
+  HIPCHK(hipMemcpyAsync(S->hd.mesh_mem + 4 * (size_t)mesh, k, 32, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(hipStreamSynchronize(S->stream));
+  if (k[0] != 0.0 || k[1] != 0.0 || k[2] != 0.0 || k[3] != 0.0) S->membrane = 1;
   return upload_simdev(S);
 }
 
@@ -868,7 +941,11 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.mesh_off = B->doffs + 2 * (n + 1);
   it.cube_off = B->doffs + 3 * (n + 1);
   it.big_templates = 0;
-  for (int i = 0; i < n; ++i) it.big_templates |= sims[i]->big_templates;
+  it.membrane = 0;
+  for (int i = 0; i < n; ++i) {
+    it.big_templates |= sims[i]->big_templates;
+    it.membrane |= sims[i]->membrane;
+  }
   it.forces_variant = forces_variant();
   it.sub = 0;
   *out = B;

@@ -69,6 +69,7 @@ def lib():
             "ibl_sim_destroy": [P],
             "ibl_template_add": [P, I32, I32, P, P, ctypes.POINTER(I32)],
             "ibl_mesh_add": [P, I32, P, D, D, ctypes.POINTER(I32)],
+            "ibl_mesh_membrane": [P, I32, D, D, D, D],
             "ibl_step": [P, I64],
             "ibl_sync": [P],
             "ibl_read_fields": [P, P, P, P],
@@ -181,6 +182,12 @@ class Sim:
         self._mesh_nn.append(x.shape[0])
         return out.value
 
+    def set_membrane(self, mesh, kbtp=0.0, kg=0.0, kl=0.0, kv=0.0):
+        """WLC-POW stretching (kbtp = kBT/p), global / local area (kg, kl) and
+        volume (kv) terms of a capsule, in addition to its springs and
+        bending (zero: term absent)."""
+        _check(lib().ibl_mesh_membrane(self.h, int(mesh), float(kbtp), float(kg), float(kl), float(kv)))
+
     # -- running ------------------------------------------------------------
     def step(self, n=1):
         _check(lib().ibl_step(self.h, int(n)))
@@ -284,7 +291,9 @@ class Sim:
             for ci in grp:
                 mesh_of[ci] = t
         for ci, c in enumerate(spec.capsules):
-            sim.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
+            m = sim.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
+            if any(c.membrane):
+                sim.set_membrane(m, *c.membrane)
         return sim
 
 

@@ -130,6 +130,7 @@ class Capsule:
     ks: float
     kb: float
     shape_key: str = ""    # capsules with equal keys share one reference state
+    membrane: tuple = (0.0, 0.0, 0.0, 0.0)  # kBT/p (WLC-POW), kg, kl (area), kv (volume)
 
 
 @dataclass

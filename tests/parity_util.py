@@ -16,7 +16,9 @@ def oracle_from_spec(spec):
         for ci in grp:
             mesh_of[ci] = t
     for ci, c in enumerate(spec.capsules):
-        s.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
+        m = s.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
+        if any(c.membrane):
+            s.set_membrane(m, *c.membrane)
     return s
 
 

@@ -1,0 +1,134 @@
+"""GPU parity of the rest of the membrane energy, Eq. (6): WLC-POW stretching
+(Eq. (7)), global and local area (Eq. (9)) and volume (Eq. (10)) terms, run
+through the C-ABI against the FP64 oracle on the same seeded capsule.
+
+The membrane-term kernel sums node forces in 64-bit fixed point at 2^-46
+(order-independent, reproducible): each of a node's shares (at most 6
+triangles and 6 bonds on these meshes) is rounded by at most 2^-47, so a node
+force differs from the FP64 sum by at most 12 * 2^-47 = 8.5e-14 plus FP64
+rounding; the bound below is 1e-12 absolute.  The spring and bending part of
+the FP32 / FP16 force kernel keeps its own 2^-40 scale (5.5e-12 per node), so
+there the bound is 2e-11."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from paper_1704_04551_amd import ibl
+from paper_1704_04551_amd import workloads as W
+from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-11, "f32": 1e-5, "f16": 1e-3}
+F_ABS = {"f64": 1e-12, "f32": 2e-11, "f16": 2e-11}
+TERMS = (1e-3, 0.01, 0.01, 0.01)  # kBT/p, kg, kl, kv
+
+
+def _spec(terms=TERMS, squeeze=0.97, steps=0):
+    """The small Couette capsule, squeezed about its centre (the area and
+    volume terms then push back) and stretched along x (the bonds pull)."""
+    spec = W.config_small(delta="cos", n=32)
+    c = spec.capsules[0]
+    cen = c.x_ref.mean(0)
+    x = cen + (c.x - cen) * squeeze * np.array([1.04, 1.0, 0.98])
+    cap = dataclasses.replace(c, x=x, ks=0.0, membrane=tuple(terms))
+    return dataclasses.replace(spec, capsules=[cap])
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_membrane_terms_force_matches_oracle(storage):
+    """Node forces at the initial positions (observation, no step): every
+    term on, springs off (the paper's model), against the oracle."""
+    spec = _spec()
+    g = ibl.Sim.from_spec(spec, storage=storage)
+    o = oracle_from_spec(spec)
+    try:
+        _, _, Fg = g.nodes(0)
+        _, _, Fo = o.nodes(0)
+        assert np.abs(Fo).max() > 1e-4
+        assert np.abs(Fg - Fo).max() < F_ABS[storage], np.abs(Fg - Fo).max()
+        # the terms act: without them the force is the bending force alone
+        spec0 = _spec(terms=(0.0, 0.0, 0.0, 0.0))
+        g0 = ibl.Sim.from_spec(spec0, storage=storage)
+        _, _, F0 = g0.nodes(0)
+        g0.close()
+        assert np.abs(Fg - F0).max() > 1e-5
+    finally:
+        g.close()
+        o.close()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16"])
+def test_membrane_terms_coupled_steps_match_oracle(storage):
+    """300 coupled steps with every term on: velocity, density, node
+    positions and forces against the oracle, at the storage's parity bar."""
+    spec = _spec()
+    g = ibl.Sim.from_spec(spec, storage=storage)
+    o = oracle_from_spec(spec)
+    try:
+        g.step(300)
+        g.sync()
+        o.step(300)
+        mask = fluid_mask(spec)
+        rg, ug, _ = g.fields()
+        ro, uo, _ = o.observe()
+        eu = field_err(ug, uo, mask)
+        assert eu[0] < TOL[storage], eu
+        assert float(np.abs(rg[mask] - ro[mask]).max()) < TOL[storage]
+        Xg, _, Fg = g.nodes(0)
+        Xo, _, Fo = o.nodes(0)
+        dx, rel = node_err(Xg, Xo, spec.capsules[0].x)
+        assert rel < TOL[storage] or dx < 1e-12, (dx, rel)
+        if storage == "f64":
+            assert np.abs(Fg - Fo).max() < F_ABS[storage]
+    finally:
+        g.close()
+        o.close()
+
+
+def test_zero_terms_are_bitwise_absent():
+    """Setting every constant to zero leaves the run bitwise unchanged."""
+    spec0 = _spec(terms=(0.0, 0.0, 0.0, 0.0))
+    a = ibl.Sim.from_spec(spec0, storage="f32")
+    b = ibl.Sim.from_spec(spec0, storage="f32")
+    try:
+        b.set_membrane(0, 0.0, 0.0, 0.0, 0.0)
+        for s in (a, b):
+            s.step(50)
+            s.sync()
+        assert np.array_equal(a.nodes(0)[0], b.nodes(0)[0])
+        assert np.array_equal(a.fields(rho=False, g=False)[1], b.fields(rho=False, g=False)[1])
+    finally:
+        a.close()
+        b.close()
+
+
+def test_membrane_argument_errors():
+    spec = _spec(terms=(0.0, 0.0, 0.0, 0.0))
+    s = ibl.Sim.from_spec(spec, storage="f32")
+    try:
+        with pytest.raises(ibl.IBLError):
+            s.set_membrane(0, -1.0, 0.0, 0.0, 0.0)
+        with pytest.raises(ibl.IBLError):
+            s.set_membrane(0, float("nan"), 0.0, 0.0, 0.0)
+        with pytest.raises(ibl.IBLError):
+            s.set_membrane(5, 0.0, 0.1, 0.0, 0.0)
+    finally:
+        s.close()
+
+
+def test_bond_beyond_maximum_length_is_flagged():
+    """A capsule inflated to 2.1 times its rest size has every bond past
+    l_m = 2 l0: the WLC-POW energy is not finite there, so the step reports
+    the force-range health bit and the run is unstable."""
+    spec = _spec(terms=(1e-3, 0.0, 0.0, 0.0), squeeze=2.1)
+    s = ibl.Sim.from_spec(spec, storage="f32")
+    try:
+        s.step(1)
+        with pytest.raises(ibl.IBLError) as e:
+            s.sync()
+        assert e.value.status == -5
+        assert s.conservation()[2] & 0x40
+    finally:
+        s.close()
