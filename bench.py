@@ -224,6 +224,39 @@ def run_served(storage, seconds, rate, step_scale, skin, seed=1005):
     return out
 
 
+# The paper's membrane energy, Eq. (6), in lattice units: kBT/p for the WLC-POW
+# stretching (its small-strain stiffness 5 C / l0 is about the linear springs'
+# ks = 0.005 at l0 ~ 1), kg, kl (area) and kv (volume).
+FULL_MEMBRANE = (1e-3, 1e-3, 1e-3, 1e-3)
+
+
+def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
+    """The same workload with the paper's whole membrane energy: WLC-POW
+    stretching in place of the linear springs, the dihedral bending, and the
+    global / local area and volume constraints.  Graph-replayed steps timed
+    like the headline, then a phase-by-phase run."""
+    import dataclasses
+    from paper_1704_04551_amd import ibl
+    caps = [dataclasses.replace(c, ks=0.0, membrane=FULL_MEMBRANE) for c in spec.capsules]
+    sp = dataclasses.replace(spec, capsules=caps)
+    sim = ibl.Sim.from_spec(sp, storage=storage, device="cuda:0", brick_x=brick_x, skin=skin)
+    try:
+        sim.step(warmup)
+        sim.sync()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.sync()
+        wall = time.perf_counter() - t0
+        phases, _ = sim.profile_phases(steps)
+        sim.sync()
+        _, _, health = sim.conservation()
+    finally:
+        sim.close()
+    return {"terms": dict(zip(("kbt_p", "kg", "kl", "kv"), FULL_MEMBRANE)), "ks": 0.0, "steps": steps,
+            "mlups": round(spec.cells * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
+            "phase_ms": {k: round(v, 5) for k, v in phases.items()}, "health": health}
+
+
 def tile_spec(spec, reps=(2, 2, 2)):
     """The cells of `spec` repeated reps[a] times along each axis (every copy
     keeps its wall clearance, so copies never overlap)."""
@@ -338,6 +371,7 @@ def main():
     ap.add_argument("--skin", type=int, default=None, choices=[0, 1],
                     help="fixed candidate-list skin (skips the autotuner)")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--membrane-steps", type=int, default=300, help="0 skips the full-membrane run")
     ap.add_argument("--serve-seconds", type=float, default=15.0, help="0 skips the served runs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
     ap.add_argument("--serve-step-scale", type=float, default=0.1)
@@ -445,6 +479,12 @@ def main():
         "health": health,
     }
     sim.close()
+    if args.membrane_steps > 0:
+        _log("full membrane: %d steps" % args.membrane_steps)
+        fm = run_full_membrane(spec, args.storage, brick_x, skin, args.membrane_steps, min(args.warmup, 20))
+        fm["membrane_kernel_ms"] = round(fm["phase_ms"]["forces"] - result["phase_ms"]["forces"], 5)
+        result["full_membrane"] = fm
+        _log("full membrane: %s" % fm)
     if not args.no_cpu:
         _log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
         result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(spec, args.cpu_steps, args.storage)
