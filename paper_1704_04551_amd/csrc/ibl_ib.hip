@@ -627,6 +627,7 @@ __device__ __forceinline__ long long mem_quant(const SimDev& S, double v) {
 
 __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restrict__ sims, Items it, int mode) {
   __shared__ long long acc[3][kLdsNodes];
+  __shared__ double xs[3][kLdsNodes];  // the capsule's positions, read once
   __shared__ double red[2][kMemThreads];
   const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
@@ -643,9 +644,15 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
     const int e0 = S.t_edge0[tm], tr0 = S.t_tri0[tm];
     const int64_t ms = (int64_t)S.maxn;
     const GLB double* X0 = S.X + off;
-    for (int i = tid; i < nn; i += kMemThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
+    for (int i = tid; i < nn; i += kMemThreads) {
+      acc[0][i] = acc[1][i] = acc[2][i] = 0;
+      xs[0][i] = X0[i];
+      xs[1][i] = X0[ms + i];
+      xs[2][i] = X0[2 * ms + i];
+    }
+    __syncthreads();
     const bool surf = kg != 0.0 || kl != 0.0 || kv != 0.0;
-    const D3 c = {X0[0], X0[ms], X0[2 * ms]};
+    const D3 c = {xs[0][0], xs[1][0], xs[2][0]};
     double cg = 0.0, cv = 0.0;
     if (surf) {  // uniform
       double As = 0.0, Vs = 0.0;
@@ -653,7 +660,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
         const GLB int* q = S.ttri + 3 * (int64_t)(tr0 + t);
         D3 p[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p[k] = {X0[q[k]] - c.x, X0[ms + q[k]] - c.y, X0[2 * ms + q[k]] - c.z};
+        for (int k = 0; k < 3; ++k) p[k] = {xs[0][q[k]] - c.x, xs[1][q[k]] - c.y, xs[2][q[k]] - c.z};
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         As += 0.5 * sqrt(dot(n, n));
         Vs += dot(p[0], cross(p[1], p[2])) / 6.0;
@@ -672,7 +679,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
       cg = kg * (red[0][0] - A0) / A0;
       cv = kv * (red[1][0] - V0) / V0;
     }
-    __syncthreads();  // accumulators cleared, sums read
+    __syncthreads();  // sums read
     if (surf) {  // uniform
       for (int t = tid; t < nt; t += kMemThreads) {
         const GLB int* q = S.ttri + 3 * (int64_t)(tr0 + t);
@@ -681,7 +688,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           v[k] = q[k];
-          p[k] = {X0[v[k]] - c.x, X0[ms + v[k]] - c.y, X0[2 * ms + v[k]] - c.z};
+          p[k] = {xs[0][v[k]] - c.x, xs[1][v[k]] - c.y, xs[2][v[k]] - c.z};
         }
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         const double nl = sqrt(dot(n, n));
@@ -704,7 +711,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
       for (int e = tid; e < ne; e += kMemThreads) {
         const GLB int* ev = S.ev + 4 * (e0 + e);
         const int v1 = ev[1], v2 = ev[2];
-        const D3 d = {X0[v2] - X0[v1], X0[ms + v2] - X0[ms + v1], X0[2 * ms + v2] - X0[2 * ms + v1]};
+        const D3 d = {xs[0][v2] - xs[0][v1], xs[1][v2] - xs[1][v1], xs[2][v2] - xs[2][v1]};
         const double l = sqrt(dot(d, d)), l0 = S.el0[e0 + e];
         const double x = l / (2.0 * l0);
         if (!(x < 1.0)) {
