@@ -10,6 +10,10 @@
 //                 takes) every edge of every capsule in parallel (FP64 shares
 //                 to scratch), then every node gathers its incident shares in a
 //                 fixed order.
+//   k_membrane    (capsules with the rest of the membrane energy of Eq. (6))
+//                 one workgroup per capsule, before the force kernel: WLC-POW
+//                 stretching, area and volume constraints summed per node in
+//                 fixed point; the force kernels add the result.
 //   Each force kernel writes the node's spreading record (stencil base,
 //   fractional offset or delta weights, F), adds the step's largest force
 //   component to the simulation's maximum, and appends the node to the
