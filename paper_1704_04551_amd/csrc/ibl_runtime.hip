@@ -543,6 +543,32 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
     }
   }
   const int ne = (int)(ev.size() / 4);
+  // Edge order for the force kernels, whose 256 threads take 256 consecutive
+  // edges at a time: the list above is sorted by (v1, v2), so neighbouring
+  // edges mostly share v1 and the lanes of a wave would add to the same LDS
+  // accumulator one after another.  Within each aligned block of 256 edges,
+  // the first edge of every v1 comes first (in v1 order), then every second
+  // one, and so on: a wave's lanes start from distinct, neighbouring nodes.
+  // Sums in fixed point do not depend on the order.
+  {
+    std::vector<int> ev2(ev.size());
+    int o = 0;
+    for (int b0 = 0; b0 < ne; b0 += 256) {
+      const int b1 = std::min(ne, b0 + 256);
+      std::vector<std::pair<int, int>> key;
+      int run = 0;
+      for (int e = b0; e < b1; ++e) {
+        run = (e > b0 && ev[4 * e + 1] == ev[4 * (e - 1) + 1]) ? run + 1 : 0;
+        key.push_back(std::make_pair(run, e));
+      }
+      std::sort(key.begin(), key.end());
+      for (const auto& k : key) {
+        for (int r = 0; r < 4; ++r) ev2[4 * (size_t)o + r] = ev[4 * (size_t)k.second + r];
+        ++o;
+      }
+    }
+    ev.swap(ev2);
+  }
   if (ne > 3 * nn) return fail(IBL_ERR_UNSUPPORTED, "more than 3 edges per node (surface of genus > 1)");
   if (S->ntmpl + 1 > S->desc.max_templates || S->tnodes + nn > S->desc.max_template_nodes ||
       S->tedges + ne > S->desc.max_template_edges || S->ttris + nt > S->desc.max_template_edges)
