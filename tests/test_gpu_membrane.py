@@ -184,3 +184,32 @@ def test_checkpoint_roundtrip_with_membrane_terms():
     finally:
         a.close()
         b.close()
+
+
+@pytest.mark.parametrize("variant", ["split", "shares"])
+def test_membrane_terms_with_alternative_force_kernels(variant, monkeypatch):
+    """The split edge / node kernels and the per-edge-share LDS kernel add
+    the membrane terms too: forces at the initial positions and 100 coupled
+    steps against the oracle (FP32 storage)."""
+    monkeypatch.setenv("IBL_FORCES", variant)
+    spec = _spec()
+    g = ibl.Sim.from_spec(spec, storage="f32")
+    o = oracle_from_spec(spec)
+    try:
+        _, _, Fg = g.nodes(0)
+        _, _, Fo = o.nodes(0)
+        assert np.abs(Fg - Fo).max() < F_ABS["f32"] + 1e-7 * np.abs(Fo).max()
+        g.step(100)
+        g.sync()
+        o.step(100)
+        mask = fluid_mask(spec)
+        _, ug, _ = g.fields()
+        _, uo, _ = o.observe()
+        assert field_err(ug, uo, mask)[0] < TOL["f32"]
+        Xg = g.nodes(0)[0]
+        Xo = o.nodes(0)[0]
+        dx, rel = node_err(Xg, Xo, spec.capsules[0].x)
+        assert rel < TOL["f32"] or dx < 1e-12, (dx, rel)
+    finally:
+        g.close()
+        o.close()
