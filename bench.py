@@ -224,20 +224,27 @@ def run_served(storage, seconds, rate, step_scale, skin, seed=1005):
     return out
 
 
-# The paper's membrane energy, Eq. (6), in lattice units: kBT/p for the WLC-POW
-# stretching (its small-strain stiffness 5 C / l0 is about the linear springs'
-# ks = 0.005 at l0 ~ 1), kg, kl (area) and kv (volume).
-FULL_MEMBRANE = (1e-3, 1e-3, 1e-3, 1e-3)
+# The paper's red blood cell constants (Sec. 3.2 and the parameter table of
+# Sec. 3.5) in lattice units of the 256x128x128 channel, whose 16-cell cells
+# are 8 um across: dx = 0.5 um, nu = 1e-6 m^2/s at tau = 0.8 (dt = 2.5e-8 s),
+# rho = 1000 kg/m^3, so the force unit is rho dx^4 / dt^2 = 1e-7 N.
+#   kBT/p = 1e-12 N on 1320 nodes, scaled by sqrt(2636 / 1280) to keep the
+#           shear modulus of Eq. (11) on the 642-node mesh: 1.435e-5;
+#   kb = 2.3e-19 J / (1e-7 N x 0.5 um) = 4.6e-6;
+#   kg = kl = 2.1e-4 N/m / (1e-7 N / 0.5 um) = 1.05e-3;
+#   kv = 2.2 N/m^2 / (1e-7 N / (0.5 um)^2) = 5.5e-6.
+FULL_MEMBRANE = (1.435e-5, 1.05e-3, 1.05e-3, 5.5e-6)  # kBT/p, kg, kl, kv
+FULL_MEMBRANE_KB = 4.6e-6
 
 
 def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
-    """The same workload with the paper's whole membrane energy: WLC-POW
-    stretching in place of the linear springs, the dihedral bending, and the
-    global / local area and volume constraints.  Graph-replayed steps timed
+    """The same workload with the paper's whole membrane energy and its red
+    blood cell constants: WLC-POW stretching in place of the linear springs,
+    the dihedral bending, and the global / local area and volume constraints.  Graph-replayed steps timed
     like the headline, then a phase-by-phase run."""
     import dataclasses
     from paper_1704_04551_amd import ibl
-    caps = [dataclasses.replace(c, ks=0.0, membrane=FULL_MEMBRANE) for c in spec.capsules]
+    caps = [dataclasses.replace(c, ks=0.0, kb=FULL_MEMBRANE_KB, membrane=FULL_MEMBRANE) for c in spec.capsules]
     sp = dataclasses.replace(spec, capsules=caps)
     sim = ibl.Sim.from_spec(sp, storage=storage, device="cuda:0", brick_x=brick_x, skin=skin)
     try:
@@ -252,7 +259,8 @@ def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
         _, _, health = sim.conservation()
     finally:
         sim.close()
-    return {"terms": dict(zip(("kbt_p", "kg", "kl", "kv"), FULL_MEMBRANE)), "ks": 0.0, "steps": steps,
+    return {"terms": dict(zip(("kbt_p", "kg", "kl", "kv"), FULL_MEMBRANE)), "ks": 0.0, "kb": FULL_MEMBRANE_KB,
+            "constants": "the paper's red blood cell values in lattice units", "steps": steps,
             "mlups": round(spec.cells * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
             "phase_ms": {k: round(v, 5) for k, v in phases.items()}, "health": health}
 
