@@ -667,7 +667,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
         for (int k = 0; k < 3; ++k) p[k] = {xs[0][q[k]] - c.x, xs[1][q[k]] - c.y, xs[2][q[k]] - c.z};
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         As += 0.5 * sqrt(dot(n, n));
-        Vs += dot(p[0], cross(p[1], p[2])) / 6.0;
+        Vs += dot(p[0], cross(p[1], p[2]));  // 6 V_j
       }
       red[0][tid] = As;
       red[1][tid] = Vs;
@@ -681,8 +681,9 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
       }
       const double A0 = S.tav0[2 * tm], V0 = S.tav0[2 * tm + 1];
       cg = kg * (red[0][0] - A0) / A0;
-      cv = kv * (red[1][0] - V0) / V0;
+      cv = kv * (red[1][0] / 6.0 - V0) / V0;
     }
+    const double ca0 = 0.5 * cg, cv6 = cv / 6.0;  // per 2 dA_j/dp and per 6 dV_j/dp
     __syncthreads();  // sums read
     if (surf) {  // uniform
       for (int t = tid; t < nt; t += kMemThreads) {
@@ -697,15 +698,15 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         const double nl = sqrt(dot(n, n));
         const double a0 = S.ta0[tr0 + t];
-        const double ca = cg + kl * (0.5 * nl - a0) / a0;
-        const D3 nh = {n.x / nl, n.y / nl, n.z / nl};
+        const double rn = 1.0 / nl;
+        // (cg + kl (A_j - A_j0) / A_j0) / 2, with the normal's 1 / |n| folded in
+        const double ca = (ca0 + 0.5 * kl * (0.5 * nl - a0) / a0) * rn;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const D3 pn = p[(k + 1) % 3], pp = p[(k + 2) % 3];
-          const D3 gA = cross(nh, sub(pp, pn));  // 2 dA_j/dp
-          const D3 gV = cross(pn, pp);           // 6 dV_j/dp
-          const double f[3] = {-(ca * 0.5 * gA.x + cv * gV.x / 6.0), -(ca * 0.5 * gA.y + cv * gV.y / 6.0),
-                               -(ca * 0.5 * gA.z + cv * gV.z / 6.0)};
+          const D3 gA = cross(n, sub(pp, pn));  // 2 |n| dA_j/dp
+          const D3 gV = cross(pn, pp);          // 6 dV_j/dp
+          const double f[3] = {-(ca * gA.x + cv6 * gV.x), -(ca * gA.y + cv6 * gV.y), -(ca * gA.z + cv6 * gV.z)};
 #pragma unroll
           for (int a = 0; a < 3; ++a) fx_add(&acc[a][v[k]], mem_quant(S, f[a]));
         }
@@ -717,14 +718,17 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
         const int v1 = ev[1], v2 = ev[2];
         const D3 d = {xs[0][v2] - xs[0][v1], xs[1][v2] - xs[1][v1], xs[2][v2] - xs[2][v1]};
         const double l = sqrt(dot(d, d)), l0 = S.el0[e0 + e];
-        const double x = l / (2.0 * l0);
+        const double rl = 1.0 / l;
+        const double x = 0.5 * l / l0;
         if (!(x < 1.0)) {
           atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
           continue;
         }
-        const double kp = 1.25 * kbtp * l0 * l0;
-        const double dUdl = kbtp * (1.0 / (4.0 * (1.0 - x) * (1.0 - x)) - 0.25 + x) - kp / (l * l);
-        const double f[3] = {dUdl * d.x / l, dUdl * d.y / l, dUdl * d.z / l};  // force on v1
+        // dU/dl = C (1 / (4 (1 - x)^2) - 1/4 + x) - k_p / l^2 with k_p = 5/4 C l0^2
+        const double r1x = 1.0 / (1.0 - x), l0l = l0 * rl;
+        const double dUdl = kbtp * (0.25 * r1x * r1x - 0.25 + x - 1.25 * l0l * l0l);
+        const double fl = dUdl * rl;
+        const double f[3] = {fl * d.x, fl * d.y, fl * d.z};  // force on v1
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const long long qf = mem_quant(S, f[a]);
