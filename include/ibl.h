@@ -78,8 +78,11 @@ typedef enum {
 #define IBL_HEALTH_OVERFLOW 0x10u    /* a brick's candidate list overflowed */
 #define IBL_HEALTH_NONFINITE_X 0x20u /* a node position is NaN or Inf */
 #define IBL_HEALTH_FORCE_RANGE 0x40u /* a membrane force share was NaN or beyond
-                                        2048 lattice units (FP32 / FP16 storage
-                                        accumulate forces in fixed point) */
+                                        its fixed-point range: 2048 lattice
+                                        units for spring and bending shares
+                                        (FP32 / FP16 storage), 32 for area,
+                                        volume and WLC-POW shares; or a bond
+                                        reached its WLC maximum length */
 
 typedef struct {
   int32_t n[3];            /* cells per axis, each >= 4 */
@@ -160,7 +163,9 @@ ibl_status ibl_mesh_add(ibl_sim sim, int32_t template_id, const double* x, doubl
  *          every bond force-free at its rest length l0;
  *   kg, kl global and local area constraints, Eq. (9), rest areas from x_ref;
  *   kv     volume constraint, Eq. (10), rest volume enclosed by x_ref.
- * A bond at or beyond l_m sets IBL_HEALTH_FORCE_RANGE and adds no force.
+ * A bond at or beyond l_m sets IBL_HEALTH_FORCE_RANGE and adds no force; so
+ * does a share component beyond 32 lattice units (it is clamped).  Node forces
+ * are summed in 64-bit fixed point at 2^-46 lattice units (reproducible).
  * Set the terms before ibl_batch_create on a batch holding the simulation.
  * Errors: IBL_ERR_ARG (unknown mesh, a negative or non-finite constant, a
  * reference shape with a degenerate triangle or no enclosed volume for a term
