@@ -42,6 +42,11 @@
 #define M_PI 3.14159265358979323846
 #endif
 
+/* Loops over cells (nodes) run in parallel only above these sizes: a small
+ * case gains nothing from threads and loses much when a core is busy. */
+#define OMP_MIN_CELLS 32768
+#define OMP_MIN_NODES 2048
+
 /* ------------------------------------------------------------------------ */
 /* D3Q19 velocity set: one rest velocity, 6 face and 12 edge neighbours.     */
 /* Weights 1/3, 1/18, 1/36 (textbook D3Q19, the lattice named in Sec. 2.1).  */
@@ -495,21 +500,28 @@ static int stencil_axis(const ogeom *G, int a, double X, int cell[4], double r[4
 
 /* Eq. (15): g(x) += sum_k F_k delta(x - X_k), delta = phi phi phi (Eq. (16)).
  * Nodes are visited in ascending order; shares on solid cells are dropped.
- * g is [3][ncell].  Returns 0, or -1 if a node is outside the admissible range. */
+ * g is [3][ncell].  Returns 0, or -1 if a node is outside the admissible range.
+ * (The four one-dimensional kernel values of each axis are evaluated once per
+ * node; the product for a stencil point is formed as phi_x phi_y phi_z.) */
 static int spread(const ogeom *G, int kind, int nn, const double *X, const double *F, double *g) {
   long nc = (long)G->n[0] * G->n[1] * G->n[2];
   for (int k = 0; k < nn; ++k) {
     int cx[4], cy[4], cz[4];
-    double rx[4], ry[4], rz[4];
+    double rx[4], ry[4], rz[4], px[4], py[4], pz[4];
     if (stencil_axis(G, 0, X[3 * k + 0], cx, rx) || stencil_axis(G, 1, X[3 * k + 1], cy, ry) ||
         stencil_axis(G, 2, X[3 * k + 2], cz, rz))
       return -1;
+    for (int i = 0; i < 4; ++i) {
+      px[i] = oracle_phi(kind, rx[i]);
+      py[i] = oracle_phi(kind, ry[i]);
+      pz[i] = oracle_phi(kind, rz[i]);
+    }
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j)
         for (int l = 0; l < 4; ++l) {
           int c[3] = {cx[i], cy[j], cz[l]};
           if (solid_at(G, c, NULL)) continue;
-          double w = oracle_phi(kind, rx[i]) * oracle_phi(kind, ry[j]) * oracle_phi(kind, rz[l]);
+          double w = px[i] * py[j] * pz[l];
           long id = cidx(G, c[0], c[1], c[2]);
           for (int a = 0; a < 3; ++a) g[a * nc + id] += w * F[3 * k + a];
         }
@@ -518,21 +530,31 @@ static int spread(const ogeom *G, int kind, int nn, const double *X, const doubl
 }
 
 /* Eq. (14): U_k = sum_x u(x) delta(x - X_k); a solid stencil cell contributes
- * its wall velocity.  u is [3][ncell]; U is [nn][3]. */
+ * its wall velocity.  u is [3][ncell]; U is [nn][3].  Each node's sum is
+ * formed by one thread in a fixed order, so the node loop runs in parallel. */
 static int interp(const ogeom *G, int kind, int nn, const double *X, const double *u, double *U) {
   long nc = (long)G->n[0] * G->n[1] * G->n[2];
+  int bad = 0;
+#pragma omp parallel for schedule(static) reduction(|| : bad) if (nn >= OMP_MIN_NODES)
   for (int k = 0; k < nn; ++k) {
     int cx[4], cy[4], cz[4];
-    double rx[4], ry[4], rz[4];
+    double rx[4], ry[4], rz[4], px[4], py[4], pz[4];
     if (stencil_axis(G, 0, X[3 * k + 0], cx, rx) || stencil_axis(G, 1, X[3 * k + 1], cy, ry) ||
-        stencil_axis(G, 2, X[3 * k + 2], cz, rz))
-      return -1;
+        stencil_axis(G, 2, X[3 * k + 2], cz, rz)) {
+      bad = 1;
+      continue;
+    }
+    for (int i = 0; i < 4; ++i) {
+      px[i] = oracle_phi(kind, rx[i]);
+      py[i] = oracle_phi(kind, ry[i]);
+      pz[i] = oracle_phi(kind, rz[i]);
+    }
     double s[3] = {0.0, 0.0, 0.0};
     for (int i = 0; i < 4; ++i)
       for (int j = 0; j < 4; ++j)
         for (int l = 0; l < 4; ++l) {
           int c[3] = {cx[i], cy[j], cz[l]};
-          double w = oracle_phi(kind, rx[i]) * oracle_phi(kind, ry[j]) * oracle_phi(kind, rz[l]);
+          double w = px[i] * py[j] * pz[l];
           double uw[3];
           if (solid_at(G, c, uw)) {
             for (int a = 0; a < 3; ++a) s[a] += w * uw[a];
@@ -543,7 +565,7 @@ static int interp(const ogeom *G, int kind, int nn, const double *X, const doubl
         }
     for (int a = 0; a < 3; ++a) U[3 * k + a] = s[a];
   }
-  return 0;
+  return bad ? -1 : 0;
 }
 
 static void geom_set(ogeom *G, const int n[3], const int wall[3], const double *ulo,
@@ -698,16 +720,20 @@ static int observe(osim *S) {
   if (S->obs_valid) return 0;  /* state unchanged since the last evaluation */
   long nc = S->nc;
   memset(S->F, 0, sizeof(double) * 3 * (size_t)S->nnode);
+  int bad = 0;
+  /* meshes are independent (each writes its own nodes' forces) */
+#pragma omp parallel for schedule(dynamic) reduction(|| : bad) if (S->nme > 1)
   for (int m = 0; m < S->nme; ++m) {
     const omesh *M = &S->me[m];
     membrane_force(&S->tm[M->tmpl], S->X + 3 * (size_t)M->off, M->ks, M->kb, S->F + 3 * (size_t)M->off);
     if (isnan(membrane_extra(&S->tm[M->tmpl], S->X + 3 * (size_t)M->off, M->kbtp, M->kg, M->kl, M->kv,
                              S->F + 3 * (size_t)M->off)))
-      return -1;
+      bad = 1;
   }
+  if (bad) return -1;
   memset(S->g, 0, sizeof(double) * 3 * (size_t)nc);
   if (spread(&S->G, S->kind, S->nnode, S->X, S->F, S->g) != 0) return -1;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nc >= OMP_MIN_CELLS)
   for (long id = 0; id < nc; ++id) {
     if (S->solid[id]) {
       S->rho[id] = 0.0;
@@ -737,7 +763,7 @@ static int step1(osim *S) {
   for (long k = 0; k < 3L * S->nnode; ++k) S->X[k] += S->U[k];
   S->obs_valid = 0;
   double om = 1.0 / S->tau, pre = 1.0 - 0.5 / S->tau;
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (nc >= OMP_MIN_CELLS)
   for (int z = 0; z < n[2]; ++z)
     for (int y = 0; y < n[1]; ++y)
       for (int x = 0; x < n[0]; ++x) {

@@ -15,6 +15,8 @@ import os
 
 import numpy as np
 
+from .workloads import template_groups
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libibl.so")
 
@@ -295,19 +297,6 @@ class Sim:
             if any(c.membrane):
                 sim.set_membrane(m, *c.membrane)
         return sim
-
-
-def template_groups(spec):
-    """Capsule indices grouped by shared template, in first-appearance order."""
-    groups, key_of = [], {}
-    for i, c in enumerate(spec.capsules):
-        if c.shape_key and c.shape_key in key_of:
-            groups[key_of[c.shape_key]].append(i)
-        else:
-            if c.shape_key:
-                key_of[c.shape_key] = len(groups)
-            groups.append([i])
-    return groups
 
 
 class Batch:

@@ -157,6 +157,21 @@ class SimSpec:
         return int(sum(c.x.shape[0] for c in self.capsules))
 
 
+def template_groups(spec):
+    """Capsule indices grouped by shared reference state (equal non-empty
+    ``shape_key``), in first-appearance order.  Every group becomes one
+    membrane template, whose rest state is that of its first capsule."""
+    groups, key_of = [], {}
+    for i, c in enumerate(spec.capsules):
+        if c.shape_key and c.shape_key in key_of:
+            groups[key_of[c.shape_key]].append(i)
+        else:
+            if c.shape_key:
+                key_of[c.shape_key] = len(groups)
+            groups.append([i])
+    return groups
+
+
 def _couette_walls(nz_wall_axis: int, u_top: float, u_bottom: float):
     """Wall velocities for plates on axis 2 moving along x."""
     u_lo = np.zeros((3, 3))

@@ -3,14 +3,14 @@ GPU library and on the FP64 oracle, and measure their difference."""
 import numpy as np
 
 import oracle
-from paper_1704_04551_amd import ibl
+from paper_1704_04551_amd.workloads import template_groups
 
 
 def oracle_from_spec(spec):
     s = oracle.OracleSim(spec.n, spec.tau, g_body=spec.g_body, wall=spec.wall, u_lo=spec.u_lo,
                          u_hi=spec.u_hi, delta=spec.delta, init_profile=spec.init_profile)
     mesh_of = {}
-    for grp in ibl.template_groups(spec):
+    for grp in template_groups(spec):
         c0 = spec.capsules[grp[0]]
         t = s.add_template(c0.tris, c0.x_ref)
         for ci in grp:

@@ -104,6 +104,76 @@ def test_poiseuille_matches_parabola_at_magic_tau():
     assert np.abs(u[1, 1:-1, 0, 0] - ana).max() < 1e-12 * ana.max()
 
 
+def _duct_profile(N, g, nu, terms=400):
+    """Fully developed flow through a square duct of side N (walls at 1/2 and
+    N + 1/2 in cell coordinates), driven by a body force g: the Fourier-series
+    solution of nu (u_yy + u_zz) = -g with u = 0 on the walls,
+    u = 16 a^2 g / (nu pi^3) sum_{n odd} (-1)^((n-1)/2) / n^3
+        [1 - cosh(n pi z / 2a) / cosh(n pi a / 2a)] cos(n pi y / 2a),
+    a = N/2, y and z from the duct's centre.  Returns u[z, y] at the cell
+    centres 1 .. N."""
+    a = N / 2.0
+    Y = np.arange(1, N + 1) - (N + 1) / 2.0
+    u = np.zeros((N, N))
+    for n in range(1, 2 * terms, 2):
+        k = n * math.pi / (2 * a)
+        # cosh(k Z) / cosh(k a) without overflow
+        cz = np.exp(k * (np.abs(Y) - a)) * (1 + np.exp(-2 * k * np.abs(Y))) / (1 + math.exp(-2 * k * a))
+        u += (-1) ** ((n - 1) // 2) / n ** 3 * (1 - cz)[:, None] * np.cos(k * Y)[None, :]
+    return 16 * a * a * g / (nu * math.pi ** 3) * u
+
+
+def test_duct_profile_reduces_to_plane_parabola():
+    """The series above without its cosh term (a duct infinitely wide) is the
+    plane Poiseuille parabola g (a^2 - y^2) / (2 nu): checks the series before
+    it is used to check the oracle."""
+    N, g, nu = 16, 1e-6, 0.1
+    u = _duct_profile(N, g, nu)
+    a = N / 2.0
+    Y = np.arange(1, N + 1) - (N + 1) / 2.0
+    # without the cosh term (an infinitely wide duct) the series is the
+    # parabola, through the identity
+    # sum_{n odd} (-1)^((n-1)/2) cos(n pi y / 2a) / n^3 = pi^3 (a^2 - y^2) / (32 a^2)
+    s = np.zeros(N)
+    for n in range(1, 4000, 2):
+        s += (-1) ** ((n - 1) // 2) * np.cos(n * math.pi * Y / (2 * a)) / n ** 3
+    assert np.abs(s - math.pi ** 3 * (a * a - Y * Y) / (32 * a * a)).max() < 1e-9
+    # symmetric in y <-> z to the series' truncation, positive inside, largest
+    # at the four centre cells
+    assert np.abs(u - u.T).max() < 1e-7 * u.max()
+    c = N // 2
+    assert u.min() > 0 and abs(u[c - 1:c + 1, c - 1:c + 1].min() - u.max()) < 1e-7 * u.max()
+
+
+def test_duct_second_order_convergence():
+    """Square duct (walls on y and z, periodic x, body force along x; the
+    geometry of the RBC channel's cross-section): two wall axes meet at the
+    edges, where cells have bounce-back links on both axes and diagonal links
+    into the corner solid cells.  The steady oracle profile converges to the
+    Fourier-series solution at second order: the max-norm error, relative to
+    the peak velocity, drops by about 4 each time the resolution doubles,
+    and is symmetric under y <-> z.  A wrong corner or edge link would leave
+    an O(1) error at the edges and break the ratio."""
+    tau, g = 0.8, 1e-6
+    nu = (tau - 0.5) / 3.0
+    errs = []
+    for N in (8, 16, 32):
+        s = oracle.OracleSim((4, N + 2, N + 2), tau, g_body=(g, 0.0, 0.0), wall=(0, 1, 1))
+        # 22 e-folds of the slowest viscous mode, nu 2 pi^2 / N^2
+        s.step(int(22 * N * N / (2 * math.pi ** 2 * nu)) + 200)
+        _, u, _ = s.observe()
+        ux = u[0, 1:-1, 1:-1, :]
+        assert np.abs(ux - ux[:, :, :1]).max() < 1e-15  # uniform along the periodic axis
+        assert np.abs(ux[:, :, 0] - ux[:, :, 0].T).max() < 1e-12 * ux.max()
+        assert np.abs(u[1:, 1:-1, 1:-1]).max() < 1e-6 * ux.max()  # no cross flow (left-over transient)
+        ana = _duct_profile(N, g, nu)
+        errs.append(np.abs(ux[:, :, 0] - ana).max() / ana.max())
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    assert all(3.4 < r < 4.6 for r in ratios), (errs, ratios)
+    assert ratios[1] > ratios[0]  # approaching 4 from below as the resolution grows
+    assert errs[-1] < 1e-3
+
+
 def _capsule_sim(n=(16, 16, 16), wall=(0, 0, 0), tau=0.8, delta="cos", gb=(0, 0, 0), ulo=None,
                  uhi=None, radius=3.0, jitter=0.05, seed=3, init_profile=0, ks=0.01, kb=0.002):
     rng = np.random.default_rng(seed)
