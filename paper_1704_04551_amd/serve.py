@@ -9,11 +9,15 @@ per *chunk* of steps.  At every chunk boundary it
 1. retires the jobs that finished: reads their node positions, health word
    and conservation sums back to the host, then frees their device arena;
    a job whose health word reports an unstable or invalid state (non-finite
-   values, a node outside the lattice) is retired at once as failed;
+   values, rho <= 0, a fluid velocity above 0.3, a node outside the lattice;
+   the timestep latches these per cell) is retired at once as failed, and so
+   is a finished job whose final health word is not clean: failed jobs count
+   neither in goodput nor in latency;
 2. admits queued jobs, first come first served, while their footprint
    (``ibl_sim_bytes``) fits in the free part of the memory pool and a slot is
-   free; a job that can never fit is rejected, and arrivals beyond the queue
-   bound are rejected on arrival;
+   free; a job that can never fit, or whose walls move faster than the
+   low-Mach bound, is rejected, and arrivals beyond the queue bound are
+   rejected on arrival;
 3. launches the next chunk: each resident job advances min(chunk, steps
    left), so jobs of different lengths finish at their own step counts.
 
@@ -36,6 +40,8 @@ import time
 from typing import Callable, List, Optional
 
 import numpy as np
+
+from . import workloads as W
 
 
 @dataclasses.dataclass
@@ -77,9 +83,23 @@ class GpuBackend:
         self._batch = None
         self._members = ()     # the batch's simulations (they must outlive it)
 
+    # lattice Boltzmann is valid at low Mach number only: the step flags any
+    # fluid velocity above this bound (health word), so a job whose walls move
+    # faster is refused at admission rather than run to a flagged result
+    MACH_BOUND = 0.3
+
+    def admissible(self, spec) -> Optional[str]:
+        vmax = 0.0
+        for a in range(3):
+            if spec.wall[a]:
+                vmax = max(vmax, float(np.linalg.norm(spec.u_lo[a])), float(np.linalg.norm(spec.u_hi[a])))
+        if vmax > self.MACH_BOUND:
+            return "wall speed %.3g above the low-Mach bound %.1f" % (vmax, self.MACH_BOUND)
+        return None
+
     def footprint(self, spec) -> int:
         ibl = self.ibl
-        groups = ibl.template_groups(spec)
+        groups = W.template_groups(spec)
         tn = sum(spec.capsules[g[0]].x.shape[0] for g in groups)
         te = sum(3 * spec.capsules[g[0]].tris.shape[0] // 2 for g in groups)
         desc = ibl.make_desc(spec.n, spec.tau, spec.g_body, spec.wall, spec.u_lo, spec.u_hi,
@@ -164,7 +184,12 @@ class Server:
     def _offer(self, job: Job):
         job.left = job.steps
         job.footprint = self.be.footprint(job.spec)
-        if job.footprint > self.pool:
+        check = getattr(self.be, "admissible", None)
+        why = check(job.spec) if check is not None else None
+        if why is not None:
+            job.rejected = why
+            self.rejected.append(job)
+        elif job.footprint > self.pool:
             job.rejected = "larger than the pool"
             self.rejected.append(job)
         elif len(self.queue) >= self.queue_cap:
@@ -204,7 +229,13 @@ class Server:
             job.handle = None
             self.used -= job.footprint
             job.done = self.clock() - t0
-            self.finished.append(job)
+            if job.result.get("health", 0):
+                # the library flagged the final state (unstable, out of range):
+                # not a result; it counts neither in goodput nor in latency
+                job.failed = "health word 0x%x" % job.result["health"]
+                self.failed.append(job)
+            else:
+                self.finished.append(job)
         self.resident = keep
 
     # -- the loop -----------------------------------------------------------

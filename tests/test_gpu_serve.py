@@ -44,3 +44,38 @@ def test_served_results_equal_alone():
         for m in range(len(j.spec.capsules)):
             assert np.array_equal(j.result["X"][m], alone.nodes(m)[0]), (j.jid, m)
         alone.close()
+
+
+def test_job_crossing_mach_bound_is_retired_as_failed():
+    """The timestep latches the Mach health bit per cell: a job whose fluid
+    accelerates past |u| = 0.3 mid-run (periodic 16^3 box, body force 1e-3,
+    so u = g (t + 1/2) crosses 0.3 at step 300) is retired as failed at the
+    chunk boundary after the crossing (step 400), and counts neither in
+    goodput nor in latency; a well-behaved job beside it finishes."""
+    bad = W.SimSpec(n=(16, 16, 16), tau=0.8, g_body=(1e-3, 0.0, 0.0), steps=1000, name="accelerating")
+    good = W.job_served(np.random.default_rng(7), edges=(32,), steps=(500, 500))
+    jobs = [Job(0, bad, arrival=0.0, steps=1000), Job(1, good, arrival=0.0, steps=good.steps)]
+    srv = Server(GpuBackend("f32"), pool_bytes=1 << 32, chunk=100, max_resident=4)
+    try:
+        st = srv.run(jobs, time_limit=120)
+    finally:
+        srv.close()
+    print("serve stats", st)
+    assert st["failed"] == 1 and st["finished"] == 1, st
+    assert jobs[0].failed == "unstable" and jobs[0].result is None
+    assert jobs[0].left == 600, jobs[0].left
+    assert jobs[1].result["health"] == 0
+
+
+def test_wall_speed_above_mach_bound_is_refused():
+    """A served job whose walls move faster than the low-Mach bound (the
+    128^3 lattice at shear rate 0.005: walls at 0.315) is refused at admission."""
+    rng = np.random.default_rng(3)
+    spec = W.job_served(rng, edges=(128,), steps=(100, 100))
+    assert np.abs(spec.u_hi).max() > 0.3
+    srv = Server(GpuBackend("f32"), pool_bytes=1 << 32, chunk=50, max_resident=4)
+    try:
+        st = srv.run([Job(0, spec, arrival=0.0, steps=100)], time_limit=60)
+    finally:
+        srv.close()
+    assert st["rejected"] == 1 and st["finished"] == 0

@@ -164,3 +164,33 @@ def test_unstable_job_is_retired_as_failed():
 def test_bad_arguments():
     with pytest.raises(ValueError):
         Server(None, 0)
+
+
+class HealthBackend(FakeBackend):
+    """Results carry a health word: jobs whose spec sets `bad_health` finish
+    with it; jobs whose spec sets `wall_speed` above 0.3 are refused."""
+
+    def admissible(self, spec):
+        v = getattr(spec, "wall_speed", 0.0)
+        return "wall speed above the low-Mach bound" if v > 0.3 else None
+
+    def result(self, sim, spec):
+        return {"steps": sim.done, "health": getattr(spec, "bad_health", 0)}
+
+
+def test_flagged_result_and_inadmissible_job_are_not_goodput():
+    """A job that ends with a non-zero health word is counted as failed (not in
+    goodput or latency); a job whose walls move faster than the low-Mach bound
+    is rejected at arrival and never takes a slot."""
+    c = Clock()
+    be = HealthBackend(c)
+    srv = Server(be, 10 ** 7, chunk=10, max_resident=8, queue_cap=100, clock=c, sleep=c.sleep)
+    jobs = [Job(i, Spec(16, 30), arrival=0.0, steps=30) for i in range(4)]
+    jobs[1].spec.bad_health = 0x4
+    jobs[3].spec.wall_speed = 0.315
+    st = srv.run(jobs)
+    assert st["finished"] == 2 and st["failed"] == 1 and st["rejected"] == 1
+    assert srv.failed[0].jid == 1 and srv.failed[0].failed == "health word 0x4"
+    assert jobs[3].rejected == "wall speed above the low-Mach bound" and jobs[3].admitted is None
+    assert st["goodput_jobs_s"] == 2 / st["wall_s"]
+    assert be.live == set() and srv.used == 0
