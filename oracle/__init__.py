@@ -51,6 +51,8 @@ def lib():
         D = ctypes.c_double
         L.oracle_phi.restype = D
         L.oracle_phi.argtypes = [I, D]
+        L.oracle_set_threads.restype = I
+        L.oracle_set_threads.argtypes = [I]
         L.oracle_membrane.restype = I
         L.oracle_membrane.argtypes = [I, I, P, P, P, D, D, P, P]
         L.oracle_membrane_full.restype = I
@@ -89,6 +91,18 @@ def lib():
         L.oracle_sim_stepcount.argtypes = [P]
         L.oracle_sim_nnodes.restype = I
         L.oracle_sim_nnodes.argtypes = [P]
+        L.oracle_mass_properties.restype = I
+        L.oracle_mass_properties.argtypes = [I, I, P, P, D, P, P, P]
+        L.oracle_body_add.restype = I
+        L.oracle_body_add.argtypes = [P, I, P, D, P, P]
+        L.oracle_body_state.restype = I
+        L.oracle_body_state.argtypes = [P, I, P, P, P, P, P, P]
+        L.oracle_body_nodes.restype = I
+        L.oracle_body_nodes.argtypes = [P, I, P, P, P]
+        L.oracle_morse.restype = D
+        L.oracle_morse.argtypes = [P, P, I, P, P, P, P]
+        L.oracle_sim_morse.restype = None
+        L.oracle_sim_morse.argtypes = [P, D, D, D, D]
         _lib = L
     return _lib
 
@@ -106,6 +120,12 @@ def _i32(a):
 
 def _p(a):
     return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count
+    they will use."""
+    return int(lib().oracle_set_threads(int(n)))
 
 
 def phi(kind, r: float) -> float:
@@ -203,6 +223,33 @@ def interp_field(n, X, u, kind="peskin4", wall=(0, 0, 0), u_lo=None, u_hi=None):
     return U
 
 
+def mass_properties(tris, x, density=1.0):
+    """(mass, centre of mass (3,), inertia tensor about it (3,3)) of a uniform
+    solid bounded by the closed outward surface (tris, x)."""
+    tris = _i32(tris)
+    x = _f64(x)
+    M = np.zeros(1)
+    c = np.zeros(3)
+    I = np.zeros((3, 3))
+    if lib().oracle_mass_properties(x.shape[0], tris.shape[0], _p(tris), _p(x), float(density), _p(M), _p(c),
+                                    _p(I)) != 0:
+        raise ValueError("not a closed surface enclosing a positive volume")
+    return float(M[0]), c, I
+
+
+def morse(n, X, obj, D0, alpha, r0, rc, wall=(0, 0, 0)):
+    """Eq. (13) between nodes of different objects (obj (m,) int): forces (m, 3)
+    and the energy, minimum image on periodic axes of the box n."""
+    n_ = _i32(n)
+    w = _i32(wall)
+    X = _f64(X)
+    ob = _i32(obj)
+    prm = _f64([D0, alpha, r0, rc])
+    F = np.zeros_like(X)
+    E = lib().oracle_morse(_p(n_), _p(w), X.shape[0], _p(X), _p(ob), _p(prm), _p(F))
+    return F, float(E)
+
+
 def velocity_set():
     c = np.zeros((19, 3), np.int32)
     w = np.zeros(19)
@@ -231,6 +278,7 @@ class OracleSim:
             raise ValueError("invalid simulation parameters")
         self._mesh_nn = []
         self._tmpl_nn = []
+        self._body_nn = []
 
     def close(self):
         if getattr(self, "_h", None):
@@ -256,6 +304,45 @@ class OracleSim:
         m = lib().oracle_mesh_add(self._h, int(tmpl), _p(x), float(ks), float(kb))
         self._mesh_nn.append(x.shape[0])
         return m
+
+    def add_body(self, tmpl, x, density=1.0, v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0)) -> int:
+        """A rigid body (Eq. (17)): the template's surface at node positions x
+        (its shape and initial pose), uniform density, initial velocity and
+        angular velocity."""
+        x = _f64(x)
+        if x.shape[0] != self._tmpl_nn[tmpl]:
+            raise ValueError("node count does not match the template")
+        v = _f64(v0)
+        w = _f64(w0)
+        b = lib().oracle_body_add(self._h, int(tmpl), _p(x), float(density), _p(v), _p(w))
+        if b < 0:
+            raise ValueError("bad body (template, density or enclosed volume)")
+        self._body_nn.append(x.shape[0])
+        return b
+
+    def body_state(self, body):
+        """dict: centre of mass xc, orientation q (w, x, y, z), velocity v,
+        angular velocity w, hydrodynamic force and torque."""
+        out = {k: np.zeros(4 if k == "q" else 3) for k in ("xc", "q", "v", "w", "force", "torque")}
+        if lib().oracle_body_state(self._h, int(body), *[_p(out[k]) for k in ("xc", "q", "v", "w", "force",
+                                                                              "torque")]) != 0:
+            raise RuntimeError("body state failed")
+        return out
+
+    def body_nodes(self, body):
+        """(X, U rigid-body node velocities, F force on the fluid), each (n, 3)."""
+        nn = self._body_nn[body]
+        X = np.zeros((nn, 3))
+        U = np.zeros((nn, 3))
+        F = np.zeros((nn, 3))
+        if lib().oracle_body_nodes(self._h, int(body), _p(X), _p(U), _p(F)) < 0:
+            raise RuntimeError("body node read failed")
+        return X, U, F
+
+    def set_morse(self, D0, alpha, r0, rc):
+        """Morse repulsion, Eq. (13), between the nodes of different capsules
+        (D0 = 0: off)."""
+        lib().oracle_sim_morse(self._h, float(D0), float(alpha), float(r0), float(rc))
 
     def set_membrane(self, mesh, kbtp=0.0, kg=0.0, kl=0.0, kv=0.0):
         """Adds the rest of the paper's membrane energy to a mesh: WLC-POW

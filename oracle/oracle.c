@@ -47,6 +47,22 @@
 #define OMP_MIN_CELLS 32768
 #define OMP_MIN_NODES 2048
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads of the parallel loops from now on (n >= 1); returns the number
+ * the loops will use (1 without OpenMP). */
+int oracle_set_threads(int n) {
+#ifdef _OPENMP
+  if (n >= 1) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* D3Q19 velocity set: one rest velocity, 6 face and 12 edge neighbours.     */
 /* Weights 1/3, 1/18, 1/36 (textbook D3Q19, the lattice named in Sec. 2.1).  */
@@ -602,6 +618,19 @@ int oracle_interp_field(const int n[3], const int wall[3], const double *ulo, co
 /* ------------------------------------------------------------------------ */
 typedef struct { int tmpl, off, nn; double ks, kb, kbtp, kg, kl, kv; } omesh;
 
+/* A rigid body (Sec. 2.3, Eq. (17)): a closed surface moved rigidly.  Node k
+ * sits at X_k = xc + R(q) r_k.  State: centre of mass xc, orientation q (unit
+ * quaternion w, x, y, z), velocity v, angular momentum L (lab frame). */
+typedef struct {
+  int tmpl, off, nn;
+  double *r;           /* [nn][3] node positions about the centre of mass, body frame */
+  double *dv;          /* [nn] node weights: a third of the incident triangles' areas
+                          times one lattice spacing */
+  double M, Ib[9], Ibinv[9];  /* mass, body-frame inertia tensor and its inverse */
+  double xc[3], q[4], v[3], L[3];
+  double force[3], torque[3];  /* hydrodynamic force and torque of the last evaluation */
+} obody;
+
 typedef struct osim {
   ogeom G;
   long nc;
@@ -614,6 +643,11 @@ typedef struct osim {
   int ntm, nme, nnode, cap_nodes;
   otmpl *tm;
   omesh *me;
+  int nbo;
+  obody *bo;
+  double *ustar;        /* [nnode][3] fluid velocity without the IB force at the nodes (bodies) */
+  double *ufree;        /* [3][nc] that velocity field */
+  double morse[4];      /* D0, alpha, r0, rc of the inter-object Morse potential (D0 = 0: off) */
   double *X, *F, *U;    /* [nnode][3] */
   long step;
   int err;
@@ -673,6 +707,8 @@ void oracle_sim_destroy(osim *S) {
   free(S->tm); free(S->me);
   free(S->f); free(S->fn); free(S->g); free(S->rho); free(S->u); free(S->solid);
   free(S->X); free(S->F); free(S->U);
+  for (int b = 0; b < S->nbo; ++b) { free(S->bo[b].r); free(S->bo[b].dv); }
+  free(S->bo); free(S->ustar); free(S->ufree);
   free(S);
 }
 
@@ -696,6 +732,7 @@ int oracle_mesh_add(osim *S, int tmpl, const double *x, double ks, double kb) {
   S->X = (double *)realloc(S->X, sizeof(double) * 3 * (size_t)(S->nnode + nn));
   S->F = (double *)realloc(S->F, sizeof(double) * 3 * (size_t)(S->nnode + nn));
   S->U = (double *)realloc(S->U, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->ustar = (double *)realloc(S->ustar, sizeof(double) * 3 * (size_t)(S->nnode + nn));
   memcpy(S->X + 3 * (size_t)S->nnode, x, sizeof(double) * 3 * (size_t)nn);
   memset(S->F + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
   memset(S->U + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
@@ -711,6 +748,348 @@ int oracle_mesh_membrane(osim *S, int mesh, double kbtp, double kg, double kl, d
   M->kbtp = kbtp; M->kg = kg; M->kl = kl; M->kv = kv;
   S->obs_valid = 0;
   return 0;
+}
+
+static int observe(osim *S);
+
+/* ------------------------------------------------------------------------ */
+/* Inter-object repulsion, Eq. (13) (Sec. 2.2): a Morse potential between    */
+/* nodes of different capsules,                                              */
+/*   U(r) = D0 [exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))],  r < rc,   */
+/* F on node i from node j = -dU/dr (X_i - X_j) / r                          */
+/*                         = 2 alpha D0 [exp(-2 alpha (r - r0))              */
+/*                                       - exp(-alpha (r - r0))] (X_i - X_j) / r. */
+/* The distance is the minimum image on periodic axes.  Every pair i < j of  */
+/* nodes of different meshes is visited once, in ascending (i, j), and its   */
+/* force added to both nodes with opposite signs.  Returns the energy.       */
+/* ------------------------------------------------------------------------ */
+static double morse_pairs(const ogeom *G, int np, const double *X, const int *obj, const double prm[4],
+                          double *F) {
+  const double D0 = prm[0], al = prm[1], r0 = prm[2], rc = prm[3];
+  double E = 0.0;
+  for (int i = 0; i < np; ++i)
+    for (int j = i + 1; j < np; ++j) {
+      if (obj[i] == obj[j]) continue;
+      double d[3];
+      for (int a = 0; a < 3; ++a) {
+        d[a] = X[3 * i + a] - X[3 * j + a];
+        if (!G->wall[a]) d[a] -= G->n[a] * floor(d[a] / G->n[a] + 0.5);
+      }
+      double r = sqrt(dot3(d, d));
+      if (!(r < rc) || r == 0.0) continue;
+      double e1 = exp(-al * (r - r0)), e2 = e1 * e1;
+      E += D0 * (e2 - 2.0 * e1);
+      double f = 2.0 * al * D0 * (e2 - e1) / r;
+      for (int a = 0; a < 3; ++a) {
+        F[3 * i + a] += f * d[a];
+        F[3 * j + a] -= f * d[a];
+      }
+    }
+  return E;
+}
+
+/* Stand-alone Morse forces and energy of np nodes (object index per node) in
+ * a box n with the given walls: F [np][3] (overwritten). */
+double oracle_morse(const int n[3], const int wall[3], int np, const double *X, const int *obj,
+                    const double prm[4], double *F) {
+  ogeom G;
+  geom_set(&G, n, wall, NULL, NULL);
+  memset(F, 0, sizeof(double) * 3 * (size_t)np);
+  return morse_pairs(&G, np, X, obj, prm, F);
+}
+
+/* Set the Morse parameters of a simulation (D0 = 0 turns it off).  It acts
+ * between the nodes of different capsules; rigid bodies do not take part. */
+void oracle_sim_morse(osim *S, double D0, double alpha, double r0, double rc) {
+  S->morse[0] = D0; S->morse[1] = alpha; S->morse[2] = r0; S->morse[3] = rc;
+  S->obs_valid = 0;
+}
+
+/* Add the Morse forces between capsules to S->F (mesh nodes only). */
+static void morse_forces(osim *S) {
+  int np = 0;
+  for (int m = 0; m < S->nme; ++m) np += S->me[m].nn;
+  double *X = (double *)calloc(3 * (size_t)np + 3, sizeof(double)), *F = (double *)calloc(3 * (size_t)np + 3, sizeof(double));
+  int *obj = (int *)calloc((size_t)np + 1, sizeof(int));
+  int k = 0;
+  for (int m = 0; m < S->nme; ++m)
+    for (int i = 0; i < S->me[m].nn; ++i, ++k) {
+      memcpy(X + 3 * k, S->X + 3 * ((size_t)S->me[m].off + i), sizeof(double) * 3);
+      obj[k] = m;
+    }
+  morse_pairs(&S->G, np, X, obj, S->morse, F);
+  k = 0;
+  for (int m = 0; m < S->nme; ++m)
+    for (int i = 0; i < S->me[m].nn; ++i, ++k)
+      for (int a = 0; a < 3; ++a) S->F[3 * ((size_t)S->me[m].off + i) + a] += F[3 * k + a];
+  free(X); free(F); free(obj);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Rigid bodies (Sec. 2.3, Eq. (17)).                                        */
+/*                                                                            */
+/* Mass properties of a uniform solid bounded by a closed, outward surface:   */
+/* the solid is the union of the tetrahedra (o, p1, p2, p3) over the          */
+/* triangles, o any fixed point (signed volumes cancel outside).  Per         */
+/* tetrahedron with o at the origin: volume p1 . (p2 x p3) / 6, centroid      */
+/* (p1 + p2 + p3) / 4 times that volume, and second moment                    */
+/*   int x x^T dV = V_t / 20 (sum_i p_i p_i^T + (sum_i p_i)(sum_i p_i)^T)     */
+/* (the canonical tetrahedron's covariance, mapped linearly).  The inertia    */
+/* tensor about the centre of mass is density (tr(C) Id - C), C the second    */
+/* moment about it.                                                           */
+/* ------------------------------------------------------------------------ */
+static int mass_props(int nn, int nt, const int *tri, const double *x, double dens, double *M,
+                      double c[3], double I[9]) {
+  const double *o = x;  /* first node */
+  double V = 0.0, cm[3] = {0.0, 0.0, 0.0}, C[9];
+  memset(C, 0, sizeof(C));
+  for (int t = 0; t < nt; ++t) {
+    double p[3][3];
+    for (int i = 0; i < 3; ++i) {
+      int v = tri[3 * t + i];
+      if (v < 0 || v >= nn) return -1;
+      for (int a = 0; a < 3; ++a) p[i][a] = x[3 * v + a] - o[a];
+    }
+    double n[3];
+    cross3(p[1], p[2], n);
+    double Vt = dot3(p[0], n) / 6.0;
+    V += Vt;
+    double sp[3];
+    for (int a = 0; a < 3; ++a) {
+      sp[a] = p[0][a] + p[1][a] + p[2][a];
+      cm[a] += Vt * sp[a] / 4.0;
+    }
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double pp = p[0][a] * p[0][b] + p[1][a] * p[1][b] + p[2][a] * p[2][b];
+        C[3 * a + b] += Vt / 20.0 * (pp + sp[a] * sp[b]);
+      }
+  }
+  if (!(V > 0.0)) return -1;
+  for (int a = 0; a < 3; ++a) cm[a] /= V;
+  /* second moment about the centre of mass, then the inertia tensor */
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C[3 * a + b] -= V * cm[a] * cm[b];
+  double tr = C[0] + C[4] + C[8];
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) I[3 * a + b] = dens * ((a == b ? tr : 0.0) - C[3 * a + b]);
+  *M = dens * V;
+  for (int a = 0; a < 3; ++a) c[a] = o[a] + cm[a];
+  return 0;
+}
+
+int oracle_mass_properties(int nn, int nt, const int *tri, const double *x, double dens, double *M,
+                           double *c, double *I) {
+  return mass_props(nn, nt, tri, x, dens, M, c, I);
+}
+
+static int inv3(const double *A, double *B) {
+  double d = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+             A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!(fabs(d) > 0.0)) return -1;
+  B[0] = (A[4] * A[8] - A[5] * A[7]) / d;
+  B[1] = (A[2] * A[7] - A[1] * A[8]) / d;
+  B[2] = (A[1] * A[5] - A[2] * A[4]) / d;
+  B[3] = (A[5] * A[6] - A[3] * A[8]) / d;
+  B[4] = (A[0] * A[8] - A[2] * A[6]) / d;
+  B[5] = (A[2] * A[3] - A[0] * A[5]) / d;
+  B[6] = (A[3] * A[7] - A[4] * A[6]) / d;
+  B[7] = (A[1] * A[6] - A[0] * A[7]) / d;
+  B[8] = (A[0] * A[4] - A[1] * A[3]) / d;
+  return 0;
+}
+
+/* Rotation matrix of the unit quaternion q = (w, x, y, z). */
+static void quat_R(const double *q, double *R) {
+  double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - z * w);     R[2] = 2 * (x * z + y * w);
+  R[3] = 2 * (x * y + z * w);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - x * w);
+  R[6] = 2 * (x * z - y * w);     R[7] = 2 * (y * z + x * w);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+static void matvec(const double *A, const double *v, double *o) {
+  for (int a = 0; a < 3; ++a) o[a] = A[3 * a] * v[0] + A[3 * a + 1] * v[1] + A[3 * a + 2] * v[2];
+}
+
+/* Angular velocity from the angular momentum: Omega = R Ib^-1 R^T L. */
+static void body_omega(const obody *B, double *w) {
+  double R[9], t[3], t2[3];
+  quat_R(B->q, R);
+  for (int a = 0; a < 3; ++a) t[a] = R[a] * B->L[0] + R[3 + a] * B->L[1] + R[6 + a] * B->L[2];  /* R^T L */
+  matvec(B->Ibinv, t, t2);
+  matvec(R, t2, w);
+}
+
+/* Node positions X_k = xc + R r_k. */
+static void body_place(obody *B, double *X) {
+  double R[9];
+  quat_R(B->q, R);
+  for (int k = 0; k < B->nn; ++k) {
+    double d[3];
+    matvec(R, B->r + 3 * k, d);
+    for (int a = 0; a < 3; ++a) X[3 * k + a] = B->xc[a] + d[a];
+  }
+}
+
+/* Add a rigid body: the template's surface at node positions x (its shape
+ * and initial placement), density dens, initial velocity v0 and angular
+ * velocity w0.  Returns the body index, or -1. */
+int oracle_body_add(osim *S, int tmpl, const double *x, double dens, const double *v0, const double *w0) {
+  if (tmpl < 0 || tmpl >= S->ntm || !(dens > 0.0)) return -1;
+  const otmpl *T = &S->tm[tmpl];
+  int nn = T->nn;
+  double M, c[3], I[9];
+  if (mass_props(nn, T->nt, T->tri, x, dens, &M, c, I) != 0) return -1;
+  S->bo = (obody *)realloc(S->bo, sizeof(obody) * (size_t)(S->nbo + 1));
+  obody *B = &S->bo[S->nbo];
+  memset(B, 0, sizeof(*B));
+  B->tmpl = tmpl; B->off = S->nnode; B->nn = nn; B->M = M;
+  memcpy(B->Ib, I, sizeof(I));
+  if (inv3(I, B->Ibinv) != 0) return -1;
+  B->r = (double *)malloc(sizeof(double) * 3 * (size_t)nn);
+  B->dv = (double *)calloc((size_t)nn, sizeof(double));
+  for (int k = 0; k < nn; ++k)
+    for (int a = 0; a < 3; ++a) B->r[3 * k + a] = x[3 * k + a] - c[a];
+  for (int t = 0; t < T->nt; ++t) {
+    const int *q = T->tri + 3 * t;
+    double At = tri_area(x + 3 * q[0], x + 3 * q[1], x + 3 * q[2]);
+    for (int i = 0; i < 3; ++i) B->dv[q[i]] += At / 3.0;  /* times one lattice spacing */
+  }
+  for (int a = 0; a < 3; ++a) {
+    B->xc[a] = c[a];
+    B->v[a] = v0 ? v0[a] : 0.0;
+  }
+  B->q[0] = 1.0; B->q[1] = B->q[2] = B->q[3] = 0.0;
+  double w[3] = {w0 ? w0[0] : 0.0, w0 ? w0[1] : 0.0, w0 ? w0[2] : 0.0};
+  matvec(B->Ib, w, B->L);  /* R = identity */
+  S->X = (double *)realloc(S->X, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->F = (double *)realloc(S->F, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->U = (double *)realloc(S->U, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  S->ustar = (double *)realloc(S->ustar, sizeof(double) * 3 * (size_t)(S->nnode + nn));
+  body_place(B, S->X + 3 * (size_t)S->nnode);
+  memset(S->F + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
+  memset(S->U + 3 * (size_t)S->nnode, 0, sizeof(double) * 3 * (size_t)nn);
+  S->nnode += nn;
+  S->obs_valid = 0;
+  return S->nbo++;
+}
+
+/* The FSI force of Eq. (17) at every node of every body, at the current
+ * state: f_k = rho_f (u(X_k) - U_k) / dt per unit volume, with u the fluid
+ * velocity before the immersed-boundary force (moments of the populations
+ * with the body force's half shift only, Eq. (3)), interpolated by Eq. (14),
+ * and U_k = v + Omega x (X_k - xc) the node's rigid-body velocity; rho_f = 1,
+ * dt = 1.  The node carries f_k dv_k; the body receives it and the fluid
+ * minus it (written to F, which the spreading takes).  Also the body's total
+ * force and torque. */
+static int body_forces(osim *S) {
+  long nc = S->nc;
+  if (!S->ufree) S->ufree = (double *)calloc(3 * (size_t)nc, sizeof(double));
+#pragma omp parallel for schedule(static) if (nc >= OMP_MIN_CELLS)
+  for (long id = 0; id < nc; ++id) {
+    if (S->solid[id]) {
+      S->ufree[id] = S->ufree[nc + id] = S->ufree[2 * nc + id] = 0.0;
+      continue;
+    }
+    double rho = 0.0, j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < 19; ++i) {
+      double fi = S->f[i * nc + id];
+      rho += fi;
+      for (int a = 0; a < 3; ++a) j[a] += fi * OC[i][a];
+    }
+    for (int a = 0; a < 3; ++a) S->ufree[a * nc + id] = (j[a] + 0.5 * S->gb[a]) / rho;
+  }
+  for (int b = 0; b < S->nbo; ++b) {
+    obody *B = &S->bo[b];
+    double *X = S->X + 3 * (size_t)B->off, *us = S->ustar + 3 * (size_t)B->off;
+    if (interp(&S->G, S->kind, B->nn, X, S->ufree, us) != 0) return -1;
+    double w[3];
+    body_omega(B, w);
+    for (int a = 0; a < 3; ++a) B->force[a] = B->torque[a] = 0.0;
+    for (int k = 0; k < B->nn; ++k) {
+      double r[3], wr[3], f[3];
+      for (int a = 0; a < 3; ++a) r[a] = X[3 * k + a] - B->xc[a];
+      cross3(w, r, wr);
+      for (int a = 0; a < 3; ++a) {
+        f[a] = B->dv[k] * (us[3 * k + a] - (B->v[a] + wr[a]));  /* on the body */
+        S->F[3 * ((size_t)B->off + k) + a] = -f[a];              /* on the fluid */
+        B->force[a] += f[a];
+      }
+      double rf[3];
+      cross3(r, f, rf);
+      for (int a = 0; a < 3; ++a) B->torque[a] += rf[a];
+    }
+  }
+  return 0;
+}
+
+/* Newton's second law for each body, with the force and torque of this step
+ * (semi-implicit Euler, dt = 1): v += F / M, L += T, xc += v; the orientation
+ * turns by the angle |Omega| about Omega, Omega = R Ib^-1 R^T L at the start
+ * of the step's orientation; the nodes are placed at the new pose. */
+static void body_advance(osim *S) {
+  for (int b = 0; b < S->nbo; ++b) {
+    obody *B = &S->bo[b];
+    for (int a = 0; a < 3; ++a) {
+      B->v[a] += B->force[a] / B->M;
+      B->L[a] += B->torque[a];
+      B->xc[a] += B->v[a];
+    }
+    double w[3];
+    body_omega(B, w);
+    double th = sqrt(dot3(w, w));
+    if (th > 0.0) {
+      double s = sin(0.5 * th) / th, dq[4] = {cos(0.5 * th), w[0] * s, w[1] * s, w[2] * s}, q[4];
+      const double *p = B->q;
+      q[0] = dq[0] * p[0] - dq[1] * p[1] - dq[2] * p[2] - dq[3] * p[3];
+      q[1] = dq[0] * p[1] + dq[1] * p[0] + dq[2] * p[3] - dq[3] * p[2];
+      q[2] = dq[0] * p[2] - dq[1] * p[3] + dq[2] * p[0] + dq[3] * p[1];
+      q[3] = dq[0] * p[3] + dq[1] * p[2] - dq[2] * p[1] + dq[3] * p[0];
+      double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+      for (int a = 0; a < 4; ++a) B->q[a] = q[a] / nq;
+    }
+    body_place(B, S->X + 3 * (size_t)B->off);
+  }
+}
+
+/* Body state: centre of mass, orientation (w, x, y, z), velocity, angular
+ * velocity, and the hydrodynamic force and torque at the current state. */
+int oracle_body_state(osim *S, int body, double *xc, double *q, double *v, double *w, double *force,
+                      double *torque) {
+  if (body < 0 || body >= S->nbo) return -1;
+  if (observe(S) != 0) return -1;
+  obody *B = &S->bo[body];
+  for (int a = 0; a < 3; ++a) {
+    if (xc) xc[a] = B->xc[a];
+    if (v) v[a] = B->v[a];
+    if (force) force[a] = B->force[a];
+    if (torque) torque[a] = B->torque[a];
+  }
+  if (q) memcpy(q, B->q, sizeof(B->q));
+  if (w) body_omega(B, w);
+  return 0;
+}
+
+/* Node positions, rigid-body velocities and FSI forces on the fluid of one
+ * body, each [nn][3]. */
+int oracle_body_nodes(osim *S, int body, double *X, double *U, double *F) {
+  if (body < 0 || body >= S->nbo) return -1;
+  if (observe(S) != 0) return -1;
+  obody *B = &S->bo[body];
+  double w[3];
+  body_omega(B, w);
+  for (int k = 0; k < B->nn; ++k) {
+    const double *x = S->X + 3 * ((size_t)B->off + k);
+    double r[3], wr[3];
+    for (int a = 0; a < 3; ++a) r[a] = x[a] - B->xc[a];
+    cross3(w, r, wr);
+    for (int a = 0; a < 3; ++a) {
+      if (X) X[3 * k + a] = x[a];
+      if (U) U[3 * k + a] = B->v[a] + wr[a];
+      if (F) F[3 * k + a] = S->F[3 * ((size_t)B->off + k) + a];
+    }
+  }
+  return B->nn;
 }
 
 /* Steps 1-4 of a timestep at the current state (no mutation of f or X):
@@ -731,6 +1110,8 @@ static int observe(osim *S) {
       bad = 1;
   }
   if (bad) return -1;
+  if (S->morse[0] != 0.0) morse_forces(S);
+  if (S->nbo && body_forces(S) != 0) return -1;
   memset(S->g, 0, sizeof(double) * 3 * (size_t)nc);
   if (spread(&S->G, S->kind, S->nnode, S->X, S->F, S->g) != 0) return -1;
 #pragma omp parallel for schedule(static) if (nc >= OMP_MIN_CELLS)
@@ -759,8 +1140,13 @@ static int step1(osim *S) {
   if (observe(S) != 0) return -1;
   long nc = S->nc;
   const int *n = S->G.n;
-  /* node update X^{n+1} = X^n + U^n (unit time step) */
-  for (long k = 0; k < 3L * S->nnode; ++k) S->X[k] += S->U[k];
+  /* node update X^{n+1} = X^n + U^n (unit time step) of the deformable
+   * meshes; rigid bodies follow Newton's law with this step's force */
+  for (int m = 0; m < S->nme; ++m) {
+    const omesh *M = &S->me[m];
+    for (long k = 3L * M->off; k < 3L * (M->off + M->nn); ++k) S->X[k] += S->U[k];
+  }
+  body_advance(S);
   S->obs_valid = 0;
   double om = 1.0 / S->tau, pre = 1.0 - 0.5 / S->tau;
 #pragma omp parallel for schedule(static) if (nc >= OMP_MIN_CELLS)
