@@ -18,7 +18,8 @@ Prints one JSON line.
   with a HIP event after each phase, on the simulation's own stream.
   Algorithmic bytes per cell update: 2 x 19 x (storage bytes).
 * ``cpu_baseline``: the FP64 oracle timed on a few steps of the same workload
-  on the host cores; the GPU run of the same steps from the same initial
+  on the host cores (and one step on a single thread, ``single_thread``); the
+  GPU run of the same steps from the same initial
   state is compared with it (``error_vs_oracle``).
 * ``batched``: 64 uneven simulations in one batched launch sequence against
   the same simulations run one after another.
@@ -94,21 +95,35 @@ def load_spec(args):
     return spec
 
 
-def cpu_baseline(spec, steps, storage):
+def cpu_baseline(spec, steps, storage, single_steps=1):
     """The oracle (FP64, OpenMP over the lattice loops) on `steps` steps of the
     workload, and the GPU's error against it after the same steps."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
     from paper_1704_04551_amd import ibl
+    import oracle
     o = oracle_from_spec(spec)
+    cores = len(os.sched_getaffinity(0))
+    threads = oracle.set_threads(int(os.environ.get("OMP_NUM_THREADS", "0")) or cores)
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
     base = {"value": spec.cells * steps / dt / 1e6, "unit": "MLUPS", "cores": threads,
             "kind": "oracle",
-            "sample": "%d FP64 oracle steps of the same %dx%dx%d workload (%d cells, %d nodes), "
+            "sample": "%d FP64 oracle steps of the same %dx%dx%d workload (%d capsules, %d nodes), "
                       "%.1f s" % (steps, *spec.n, len(spec.capsules), spec.nodes, dt)}
+    if single_steps > 0:
+        # the same oracle on one thread, on a copy of the workload
+        o1 = oracle_from_spec(spec)
+        oracle.set_threads(1)
+        t0 = time.perf_counter()
+        o1.step(single_steps)
+        d1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        o1.close()
+        base["single_thread"] = {"value": spec.cells * single_steps / d1 / 1e6, "unit": "MLUPS", "cores": 1,
+                                 "sample": "%d FP64 oracle step(s) of the same workload on one thread, %.1f s"
+                                           % (single_steps, d1)}
     g = ibl.Sim.from_spec(spec, storage=storage)
     g.step(steps)
     g.sync()
@@ -370,7 +385,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--storage", default="f32", choices=["f32", "f16", "f64"])
     ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-single-steps", type=int, default=1, help="oracle steps of the one-thread leg")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-capsules", action="store_true",
+                    help="the lattice of the workload without its capsules (profiling aid)")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the built-in brick width and no skin (or --brick-x / --skin)")
@@ -397,14 +415,32 @@ def main():
                          "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.copy_probe:
+        # the library's plain streaming copy kernel: the practical HBM ceiling
+        # (read + written bytes over the mean launch time, HIP events on
+        # torch's stream, the one the copy is launched on) and the calibration
+        # of a profiler's byte counters
         import torch
+        from paper_1704_04551_amd import ibl
         n = args.copy_probe * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
-        for _ in range(5):
-            dst.copy_(src)
+        for _ in range(3):
+            ibl.hbm_copy(src, dst)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": 5}))
+        reps = 20
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+        ev[0].record()
+        for i in range(reps):
+            ibl.hbm_copy(src, dst)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
+        assert bool(torch.equal(src, dst))
+        ms_mean = sum(ms) / reps
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": reps + 3,
+                          "ms_mean": round(ms_mean, 5), "ms_min": round(min(ms), 5),
+                          "gbps_mean": round(8 * n / ms_mean / 1e6, 1),
+                          "gbps_best": round(8 * n / min(ms) / 1e6, 1)}))
         return
     if args.precision_sweep:
         precision_sweep(args)
@@ -420,6 +456,11 @@ def main():
 
     _log("generating workload")
     spec = load_spec(args)
+    if args.no_capsules:
+        # the same lattice without its capsules: collide-stream alone (a
+        # profiling aid for the lattice kernel, not the workload's figure)
+        import dataclasses
+        spec = dataclasses.replace(spec, capsules=[], name=spec.name + "-no-capsules")
     tuned = None
     brick_x, skin = args.brick_x, args.skin
     if not brick_x and skin is None and not args.no_autotune:
@@ -494,8 +535,9 @@ def main():
         result["full_membrane"] = fm
         _log("full membrane: %s" % fm)
     if not args.no_cpu:
-        _log("cpu baseline (oracle, %d steps)" % args.cpu_steps)
-        result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(spec, args.cpu_steps, args.storage)
+        _log("cpu baseline (oracle, %d steps, then %d on one thread)" % (args.cpu_steps, args.cpu_single_steps))
+        result["cpu_baseline"], result["error_vs_oracle"] = cpu_baseline(spec, args.cpu_steps, args.storage,
+                                                                         args.cpu_single_steps)
     if not args.no_batched:
         _log("batched: 64 uneven simulations, %d steps" % args.batched_steps)
         runs = {k: run_batched(args.storage, args.batched_steps, k) for k in (0, 1)}

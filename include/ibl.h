@@ -55,13 +55,24 @@ typedef enum {
 
 /* Population storage.  Every mode stores the offset of each population from
  * its rest equilibrium, h_i = f_i - w_i, so that low-Mach populations keep
- * their significant bits.  Collision arithmetic is FP64 for IBL_F64 and FP32
- * otherwise; node positions, membrane forces and conservation sums are FP64
- * in every mode. */
+ * their significant bits.
+ *   - Collision arithmetic: FP64 for IBL_F64; for IBL_F32 the moments and the
+ *     O(u) part of each post-collision value in FP64, the O(u^2) and forcing
+ *     terms in FP32; FP32 for IBL_F16_OFFSET.
+ *   - Stores of the timestep round stochastically (up with probability equal
+ *     to the discarded fraction, to within 2^-16 of an ulp for binary32 and
+ *     2^-13 for binary16) with random bits hashed from (cell, step,
+ *     population), so runs are bitwise reproducible.  Values below the
+ *     format's normal range, and the initial state, round to nearest.
+ *   - Node positions and the conservation sums are FP64 in every mode.
+ *     Membrane forces are computed in FP64; with FP32 / FP16 storage each
+ *     node's sum is formed in 64-bit fixed point (2^-40 lattice units) and
+ *     the spreading carries it as binary32. */
 typedef enum {
-  IBL_F64 = 0,        /* h_i = f_i - w_i as binary64 (parity form) */
-  IBL_F32 = 1,        /* h_i = f_i - w_i as binary32 */
-  IBL_F16_OFFSET = 2  /* h_i = f_i - w_i as binary16 (round to nearest even) */
+  IBL_F64 = 0,        /* h_i as binary64 (parity form) */
+  IBL_F32 = 1,        /* h_i as binary32 */
+  IBL_F16_OFFSET = 2  /* 2^16 h_i as binary16: the exact power-of-two scale puts
+                         offsets from 2^-30 to 0.9995 in binary16's normal range */
 } ibl_storage;
 
 /* One-dimensional delta kernel phi(r), 4-point support (Sec. 2.3). */
@@ -70,7 +81,9 @@ typedef enum {
   IBL_DELTA_PESKIN4 = 1  /* Peskin's 4-point kernel (zero first moment) */
 } ibl_delta;
 
-/* Health word bits (ibl_conservation). */
+/* Health word bits (ibl_sync, ibl_conservation).  The timestep latches the
+ * population bits (non-finite, rho, Mach) per fluid cell and the node bits per
+ * node as it runs; ibl_conservation re-checks the stored populations. */
 #define IBL_HEALTH_NONFINITE_F 0x1u  /* a population is NaN or Inf */
 #define IBL_HEALTH_RHO 0x2u          /* rho <= 0 in a fluid cell */
 #define IBL_HEALTH_MACH 0x4u         /* |u| > 0.3 in a fluid cell */
@@ -111,6 +124,8 @@ typedef struct {
                               stencil base has moved more than one cell from where it was
                               at the last build.  A tuning knob: results are bitwise
                               identical either way. */
+  int32_t morse;           /* 1: reserve the neighbour grid of the inter-capsule Morse
+                              repulsion (ibl_sim_morse); 0: none */
 } ibl_sim_desc;
 
 typedef struct ibl_sim_s* ibl_sim;
@@ -155,6 +170,37 @@ ibl_status ibl_template_add(ibl_sim sim, int32_t n_nodes, int32_t n_tris, const 
 ibl_status ibl_mesh_add(ibl_sim sim, int32_t template_id, const double* x, double ks, double kb,
                         int32_t* out_mesh);
 
+/* Add a rigid body (Sec. 2.3, Eq. (17)): the template's closed surface at node
+ * positions x, host FP64 [n_nodes][3] (copied), which fix the body's shape
+ * and initial pose, moving as one body of uniform density `density` (the
+ * fluid's is 1) with initial velocity v0[3] and angular velocity w0[3]
+ * (either may be NULL: zero).  The body counts as a mesh (its index is
+ * returned in out_mesh; ibl_read_nodes gives its node positions, rigid-body
+ * node velocities and FSI forces on the fluid).  Each step:
+ *   - the fluid velocity before the immersed-boundary force, u* = (sum f c +
+ *     g_body / 2) / rho, is interpolated at every node X_k (Eq. (14));
+ *   - the FSI force of Eq. (17), rho_f (u* - U_k) / dt with rho_f = dt = 1,
+ *     U_k = v + Omega x (X_k - x_c), times the node's weight (a third of its
+ *     triangles' areas times one lattice spacing) acts on the body, and its
+ *     opposite is spread onto the fluid (Eq. (15));
+ *   - Newton's second law with the summed force and torque about the centre
+ *     of mass, semi-implicit Euler with dt = 1: v += F / M, L += T,
+ *     x_c += v, the orientation turned by |Omega| about Omega = R I^-1 R^T L;
+ *     mass, centre of mass and inertia tensor are those of the uniform solid
+ *     the surface bounds.
+ * Errors: IBL_ERR_ARG (bad template, density <= 0, non-finite values, a node
+ * outside the admissible range, a surface enclosing no volume),
+ * IBL_ERR_NOMEM (node or mesh capacity). */
+ibl_status ibl_body_add(ibl_sim sim, int32_t template_id, const double* x, double density, const double* v0,
+                        const double* w0, int32_t* out_mesh);
+
+/* State of a rigid body at the current time N, out[19] host FP64: centre of
+ * mass [0..2], orientation quaternion (w, x, y, z) relative to the pose given
+ * at ibl_body_add [3..6], velocity [7..9], angular velocity [10..12], and the
+ * hydrodynamic force [13..15] and torque about the centre of mass [16..18] of
+ * Eq. (17) at state N.  Synchronous.  Errors: IBL_ERR_ARG (not a body). */
+ibl_status ibl_read_body(ibl_sim sim, int32_t mesh, double* out);
+
 /* Add the rest of the paper's membrane energy, Eq. (6), to a capsule (all
  * zero after ibl_mesh_add; zero: term absent).  They add to the springs and
  * bending of ibl_mesh_add (pass ks = 0 there for the paper's model):
@@ -165,19 +211,34 @@ ibl_status ibl_mesh_add(ibl_sim sim, int32_t template_id, const double* x, doubl
  *   kv     volume constraint, Eq. (10), rest volume enclosed by x_ref.
  * A bond at or beyond l_m sets IBL_HEALTH_FORCE_RANGE and adds no force; so
  * does a share component beyond 32 lattice units (it is clamped).  Node forces
- * are summed in 64-bit fixed point at 2^-46 lattice units (reproducible).
- * Set the terms before ibl_batch_create on a batch holding the simulation.
- * Errors: IBL_ERR_ARG (unknown mesh, a negative or non-finite constant, a
- * reference shape with a degenerate triangle or no enclosed volume for a term
- * that needs it), IBL_ERR_UNSUPPORTED (template beyond the LDS force kernel,
- * more than 642 nodes or 1920 edges). */
+ * are summed in 64-bit fixed point at 2^-46 lattice units (reproducible, and
+ * the same for templates of any size: above 642 nodes the sums are kept in
+ * HBM instead of LDS).  Set the terms before ibl_batch_create on a batch
+ * holding the simulation.  Errors: IBL_ERR_ARG (unknown mesh or a rigid body,
+ * a negative or non-finite constant, a reference shape with a degenerate
+ * triangle or no enclosed volume for a term that needs it). */
 ibl_status ibl_mesh_membrane(ibl_sim sim, int32_t mesh, double kbt_p, double kg, double kl, double kv);
+
+/* Inter-capsule repulsion (Sec. 2.2, Eq. (13)): the Morse potential
+ * U(r) = D0 [exp(-2 alpha (r - r0)) - 2 exp(-alpha (r - r0))] for r < rc between
+ * the nodes of different capsules (rigid bodies do not take part), distances
+ * by minimum image on periodic axes.  Its force on each node is added to the
+ * membrane force before spreading.  D0 = 0 turns it off.  Neighbours are
+ * found on a grid of cells at least 2 lattice units wide, at most 48 nodes per
+ * cell (IBL_HEALTH_OVERFLOW beyond); pair forces are summed per node in 64-bit
+ * fixed point (2^-44 lattice units), so the sums are reproducible and the
+ * pair forces cancel exactly.  Errors: IBL_ERR_ARG (negative or non-finite
+ * D0, alpha <= 0, rc <= 0), IBL_ERR_UNSUPPORTED (rc > 2 lattice units, or a
+ * simulation created with morse = 0). */
+ibl_status ibl_sim_morse(ibl_sim sim, double D0, double alpha, double r0, double rc);
 
 /* Advance n_steps coupled timesteps, asynchronously on the simulation's
  * stream (replayed HIP graphs).  State afterwards: (f^N, X^N). */
 ibl_status ibl_step(ibl_sim sim, int64_t n_steps);
 
-/* Wait for the stream; report latched device failures. */
+/* Wait for the stream; report latched device failures (the health word:
+ * IBL_ERR_UNSTABLE for non-finite values, rho <= 0, |u| > 0.3 or a force out
+ * of range; IBL_ERR_STATE for a node out of range or a list overflow). */
 ibl_status ibl_sync(ibl_sim sim);
 
 /* Observables at the current time N, computed with the membrane force at X^N
@@ -199,7 +260,7 @@ ibl_status ibl_read_nodes(ibl_sim sim, int32_t mesh, double* x, double* u, doubl
 ibl_status ibl_conservation(ibl_sim sim, double* mass, double momentum[3], uint32_t* health);
 
 /* Checkpoint: bytes of the serialized state (populations in storage format,
- * node positions, step counter). */
+ * node positions, rigid-body states, step counter). */
 ibl_status ibl_state_bytes(ibl_sim sim, size_t* out_bytes);
 /* Copy the state to a caller-owned host buffer of at least ibl_state_bytes.  */
 ibl_status ibl_read_state(ibl_sim sim, void* host_buf, size_t bytes);
@@ -233,6 +294,16 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n_sims, ibl_batch* out)
 /* Advance simulation i by steps_per_sim[i] >= 0 steps (uneven allowed). */
 ibl_status ibl_batch_step(ibl_batch batch, const int64_t* steps_per_sim);
 ibl_status ibl_batch_destroy(ibl_batch batch);
+
+/* Calibration of the memory system, outside the method: a plain streaming
+ * copy of `bytes` bytes from device buffer src to device buffer dst (16-byte
+ * vector loads and stores, every workgroup striding over the whole range), on
+ * hip_stream (null: the default stream), asynchronous.  Its duration gives
+ * the practical HBM ceiling against which the kernels' bandwidth is read, and
+ * its profiler byte counters the scale factor of theirs.  Errors:
+ * IBL_ERR_ARG (null buffer, a size or an address not a multiple of 16),
+ * IBL_ERR_DEVICE. */
+ibl_status ibl_hbm_copy(const void* src, void* dst, size_t bytes, void* hip_stream);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* ibl_last_error(void);

@@ -19,63 +19,94 @@ namespace {
 // Every storage mode keeps the offset h_i = f_i - w_i (the equilibrium at rest
 // subtracted): at low Mach number f_i differs from w_i only in its low bits,
 // and a body-force increment of 1e-6 added to f_i ~ 0.05 would lose most of
-// its bits in binary32.  Offsets keep them.  FP16 stores h_i as binary16
-// (round to nearest even); FP32 and FP64 store it at full width.
+// its bits in binary32.  Offsets keep them.  FP16 stores 2^16 h_i as binary16
+// (see Store<kF16>), FP32 h_i as binary32, FP64 h_i as binary64.
+//
+// The timestep forms each post-collision value (its O(u) part in FP64 for FP32
+// storage, see k_lattice) and stores it with stochastic rounding to the
+// storage format.  In a steady or
+// slowly varying flow the same populations recur step after step, so a
+// deterministic rounding error -- of FP32 arithmetic, or of a round-to-nearest
+// store -- is the same every step and acts as a spurious force: about one
+// binary32 ulp of h (1e-10) against per-step force increments of about 1e-7.
+// Rounding up with probability equal to the discarded fraction makes each
+// store unbiased.  The random bits come from a hash of (cell, step), so runs
+// stay bitwise reproducible.
+//
+// The rounding works on the bit pattern of the computed value: random bits are
+// added just below the last bit the target format keeps, and the bits below
+// it are cleared; the carry rounds the magnitude up with probability equal to
+// the discarded fraction (to within 2^-16 of an ulp for FP32 storage, 2^-13
+// for FP16), for either sign.  The result has the target's significand width
+// and converts exactly.  (Below the target's normal range the conversion then
+// rounds to nearest.)
 //
 // A step reads each stored population once and writes each once, and the
 // next read comes a whole step later, after more traffic than the caches
 // hold: the timestep's population loads and stores are non-temporal, so the
 // caches keep what is re-read within the step (the velocity tiles of the
 // interpolation, the spreading records and candidate lists).
+
+// Stochastic rounding of v to `keep` significand bits (52 - drop), given 16
+// uniform random bits r16 (the low 16 bits of the argument).
+template <int kDrop>
+__device__ __forceinline__ double sr_truncate(double v, uint32_t r16) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint64_t t = (b + ((uint64_t)(r16 & 0xffffu) << (kDrop - 16))) & ~((1ull << kDrop) - 1ull);
+  return __longlong_as_double((long long)t);
+}
+
 template <int ST>
 struct Store;
 template <>
 struct Store<kF64> {
   using T = double;
   using R = double;
+  using D = double;
   __device__ static R h(const GLB T* p, int64_t i, int) { return __builtin_nontemporal_load(p + i); }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { __builtin_nontemporal_store(hq, p + i); }
+  __device__ static void put_sr(GLB T* p, double v, uint32_t) { __builtin_nontemporal_store(v, p); }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return p[i]; }
 };
 template <>
 struct Store<kF32> {
   using T = float;
   using R = float;
+  using D = double;
   __device__ static R h(const GLB T* p, int64_t i, int) { return __builtin_nontemporal_load(p + i); }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
-  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t, int) { __builtin_nontemporal_store(hq, p + i); }
+  // binary32 keeps 23 of the 52 fraction bits
+  __device__ static void put_sr(GLB T* p, double v, uint32_t r16) {
+    __builtin_nontemporal_store((float)sr_truncate<29>(v, r16), p);
+  }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)p[i]; }
 };
+// binary16 holds 2^16 h_i: a power-of-two scale (exact) that moves the
+// binary16 normal range, [2^-14, 65504], to offsets in [2^-30, 0.9995]
+// (|h_i| stays below 0.1 at the Mach bound of 0.3), so the small offsets of a
+// slow or resting flow keep the full 11-bit significand instead of the
+// subnormals' fixed 2^-24 spacing.
+constexpr double kF16Scale = 0x1p16;
 template <>
 struct Store<kF16> {
   using T = __half;
   using R = float;
+  using D = float;
   // binary16 moved as its 16 bits
   __device__ static R h(const GLB T* p, int64_t i, int) {
-    return __half2float(__ushort_as_half(__builtin_nontemporal_load((const GLB unsigned short*)p + i)));
+    return __half2float(__ushort_as_half(__builtin_nontemporal_load((const GLB unsigned short*)p + i))) *
+           (float)(1.0 / kF16Scale);
   }
   __device__ static void put(GLB T* p, int64_t i, int, R hq) {
-    ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn(hq));
+    ((GLB unsigned short*)p)[i] = __half_as_ushort(__float2half_rn((float)((double)hq * kF16Scale)));
   }
-  // Stochastic rounding to binary16 for the timestep's stores: a per-step
-  // increment below half a binary16 ulp (a small body force on offsets of
-  // ~1e-3) is lost every step under round-to-nearest; rounding up with
-  // probability equal to the discarded fraction keeps its expected value.
-  // The random bits hash (cell, step, population), so runs stay bitwise
-  // reproducible.
-  // `salt` is a per-(cell, step) hash; each population mixes in its own index.
-  __device__ static void put_sr(GLB T* p, int64_t i, R hq, uint32_t salt, int q) {
-    uint32_t r = (salt ^ ((uint32_t)q * 0x9E3779B9u)) * 0x2c1b3c6du;
-    r ^= r >> 13;
-    const uint32_t b = __float_as_uint(hq), a = b & 0x7fffffffu;
-    // binary16 normal range: add 13 random bits below its last mantissa bit,
-    // then drop them (the result is a binary16 value, converted exactly);
-    // subnormal, zero and out-of-range values round to nearest
-    const bool normal = a >= 0x38800000u && a < 0x477fe000u;
-    const uint32_t t = ((a + (r & 0x1fffu)) & ~0x1fffu) | (b & 0x80000000u);
-    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(normal ? __uint_as_float(t) : hq)),
-                                (GLB unsigned short*)p + i);
+  // binary16 keeps 10 of binary32's 23 fraction bits: 13 random bits are added
+  // below the last kept bit and the 13 bits cleared (on the FP32 bit pattern,
+  // as sr_truncate does on FP64)
+  __device__ static void put_sr(GLB T* p, float v, uint32_t r16) {
+    const uint32_t b = __float_as_uint(v * (float)kF16Scale);
+    const float o = __uint_as_float((b + (r16 & 0x1fffu)) & ~0x1fffu);
+    __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(o)), (GLB unsigned short*)p);
   }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
 };
@@ -303,6 +334,58 @@ __device__ __forceinline__ void reset_list_control(const SimDev& S) {
 __device__ __forceinline__ bool solid_cell(const SimDev& S, int x, int y, int z) {
   return (S.wall[0] && (x == 0 || x == S.n[0] - 1)) || (S.wall[1] && (y == 0 || y == S.n[1] - 1)) ||
          (S.wall[2] && (z == 0 || z == S.n[2] - 1));
+}
+
+// -------------------------------------------------------------- streaming --
+// The populations are stored post-collision (f* of the previous step) and
+// streamed on read ("pull"): f_q(x) = f*_q(x - c_q).  Where x - c_q is a wall
+// layer, halfway bounce-back returns the cell's own opposite population with
+// the moving-wall term: f_q(x) = f*_opp(q)(x) + 6 w_q (c_q . u_wall), u_wall
+// the velocity of the first wall axis (x, y, z order) whose layer x - c_q is.
+// The slot f*_opp(q)(x) of such a link is read by that bounce-back only (its
+// streaming neighbour is solid), so the collision stores it with the wall term
+// already added, in FP64 before the one rounding to the storage format; the
+// pull then reads every population as stored.  Writes are aligned (each cell
+// writes its own populations); only the reads are shifted.
+
+// Source of direction q for fluid cell (x, y, z): the element index of the
+// value to read, and the bounce-back wall layer (2 * axis + [hi side]) or -1.
+// Cell indices fit in 32 bits (the descriptor check bounds the lattice).
+__device__ __forceinline__ int pull_source(const SimDev& S, int q, int x, int y, int z, int cell, int& layer) {
+  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
+  const int xs = x - kCx[q], ys = y - kCy[q], zs = z - kCz[q];
+  const int sy = nx, sz = nx * ny;
+  int sc = cell - kCx[q] - sy * kCy[q] - sz * kCz[q];
+  // periodic wrap: one axis length in index units (nx, nx ny, nx ny nz)
+  if (kCx[q] && !S.wall[0]) sc += xs < 0 ? nx : (xs >= nx ? -nx : 0);
+  if (kCy[q] && !S.wall[1]) sc += ys < 0 ? sz : (ys >= ny ? -sz : 0);
+  if (kCz[q] && !S.wall[2]) sc += zs < 0 ? (int)S.ncell : (zs >= nz ? -(int)S.ncell : 0);
+  const bool bx = kCx[q] && S.wall[0] && (xs == 0 || xs == nx - 1);
+  const bool by = kCy[q] && S.wall[1] && (ys == 0 || ys == ny - 1);
+  const bool bz = kCz[q] && S.wall[2] && (zs == 0 || zs == nz - 1);
+  layer = bx ? (xs != 0) : (by ? 2 + (ys != 0) : (bz ? 4 + (zs != 0) : -1));
+  return layer >= 0 ? cell : sc;
+}
+
+// The 19 pulled populations of fluid cell (x, y, z) in the storage's compute
+// type (bounce-back links include their wall term, see above).
+template <int ST>
+__device__ __forceinline__ void pull_cell(const SimDev& S, const GLB typename Store<ST>::T* src, int x, int y,
+                                          int z, int64_t cell, RealOf<ST> h[kQ]) {
+  using T = typename Store<ST>::T;
+  const int64_t nc = S.ncell;
+  // branch-free addresses, so the 19 loads issue together.  Each load is a
+  // uniform base (population min(q, opp q)) plus a 32-bit byte offset: the
+  // descriptor check keeps 2 ncell elements below 2^32 bytes.
+#pragma unroll
+  for (int q = 0; q < kQ; ++q) {
+    int layer;
+    const int sc = pull_source(S, q, x, y, z, (int)cell, layer);
+    const int plo = q < opp(q) ? q : opp(q);
+    const uint32_t el = (uint32_t)(((layer >= 0 ? opp(q) : q) - plo) * (int)nc + sc);
+    const GLB char* base = (const GLB char*)(src + (int64_t)plo * nc);
+    h[q] = Store<ST>::h((const GLB T*)(base + el * (uint32_t)sizeof(T)), 0, q);
+  }
 }
 
 }  // namespace

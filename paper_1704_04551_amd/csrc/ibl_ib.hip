@@ -64,14 +64,14 @@ __device__ __forceinline__ void write_record(const SimDev& S, int gid, const int
 // the node update in registers.
 template <typename R>
 __device__ void make_record(const SimDev& S, int gid, const double Xp[3], const double Fv[3], int base[3],
-                            int& valid, int mode) {
+                            int& valid, int mode, int kind = 1) {
   const int64_t ms = (int64_t)S.maxn;
   if (mode == 1) {
     S.F[gid] = Fv[0];
     S.F[ms + gid] = Fv[1];
     S.F[2 * ms + gid] = Fv[2];
   }
-  valid = 1;
+  valid = kind;  // 1: a capsule's node, 2: a rigid body's (spread, never interpolated)
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     if (!isfinite(Xp[a])) {
@@ -165,9 +165,9 @@ __device__ __forceinline__ ListStep list_step(const SimDev& S, const Items& it, 
 // its list entries.  `fbits` collects the largest force component (float bits).
 template <typename R>
 __device__ void emit_node(const SimDev& S, const ListStep& L, int gid, const double Xp[3], const double Fv[3],
-                          int mode, uint32_t& fbits) {
+                          int mode, uint32_t& fbits, int kind = 1) {
   int base[3], valid;
-  make_record<R>(S, gid, Xp, Fv, base, valid, mode);
+  make_record<R>(S, gid, Xp, Fv, base, valid, mode, kind);
   const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
   const uint32_t fb = __float_as_uint(isfinite(fm) ? fm : 0.f);
   fbits = fb > fbits ? fb : fbits;
@@ -332,13 +332,13 @@ __device__ void append_rare(const SimDev& S, int buf, const NodeBricks& nb, int 
 // required.
 template <typename R>
 __device__ void emit_nodes(const SimDev& S, BinTable& T, const ListStep& L, bool active, int gid,
-                           const double Xp[3], const double Fv[3], int mode, uint32_t& fbits) {
+                           const double Xp[3], const double Fv[3], int mode, uint32_t& fbits, int kind = 1) {
   NodeBricks nb;
   nb.mask = 0;
   nb.rare = 0;
   if (active) {
     int base[3], valid;
-    make_record<R>(S, gid, Xp, Fv, base, valid, mode);
+    make_record<R>(S, gid, Xp, Fv, base, valid, mode, kind);
     const float fm = (float)fmax(fabs(Fv[0]), fmax(fabs(Fv[1]), fabs(Fv[2])));
     const uint32_t fb = __float_as_uint(isfinite(fm) ? fm : 0.f);
     fbits = fb > fbits ? fb : fbits;
@@ -417,10 +417,17 @@ __device__ __forceinline__ bool mesh_has_terms(const SimDev& S, int m) {
 
 __device__ __forceinline__ void add_membrane_terms(const SimDev& S, const Items& it, int m, bool act, int gid,
                                                    double F[3]) {
-  if (!it.membrane || !act || !mesh_has_terms(S, m)) return;
   const int64_t ms = (int64_t)S.maxn;
+  if (it.membrane && act && mesh_has_terms(S, m)) {
 #pragma unroll
-  for (int a = 0; a < 3; ++a) F[a] += S.Fext[a * ms + gid];
+    for (int a = 0; a < 3; ++a) F[a] += S.Fext[a * ms + gid];
+  }
+  // the inter-capsule Morse force of the step (k_morse_force), after the
+  // membrane's own terms
+  if (it.morse && act && S.morse[0] != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) F[a] += S.Fm[a * ms + gid];
+  }
 }
 
 template <typename R>
@@ -446,6 +453,7 @@ __global__ __launch_bounds__(forces_threads<R>()) void k_forces_lds(const SimDev
     const GLB double* X0 = S.X + off;
     const ListStep L = list_step(S, it, mode);
     clear_next_rebuild(S, L, m, mode);
+    if (S.mesh_rigid[m]) continue;  // a rigid body (k_rigid_nodes); uniform
     for (int e = tid; e < ne; e += NT) {
       const GLB int* v = S.ev + 4 * (e0 + e);
       D3 p[4];
@@ -541,6 +549,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
     const GLB double* X0 = S.X + off;
     const ListStep L = list_step(S, it, mode);
     clear_next_rebuild(S, L, m, mode);
+    if (S.mesh_rigid[m]) continue;  // a rigid body (k_rigid_nodes); uniform
     for (int i = tid; i < nn; i += kFxThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
     __syncthreads();
     for (int e = tid; e < ne; e += kFxThreads) {
@@ -617,6 +626,10 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
 // units (health bit beyond), one rounding of at most 2^-47 = 7.1e-15 per
 // share, well inside FP64 parity.  A bond at or beyond its maximum length has
 // no finite energy: it sets the force-range health bit and contributes nothing.
+// Templates beyond the LDS arrays (kBig) read the positions from HBM and sum
+// the same fixed-point shares with 64-bit integer atomics in the capsule's
+// own Fext range (zeroed first, converted to doubles in place at the end):
+// integer sums, so the result is the same as the LDS kernel's.
 constexpr int kMemThreads = 256;
 constexpr double kMemLimit = 32.0;  // |share component| limit: 2^5 = 2^(51 - 46)
 
@@ -629,9 +642,11 @@ __device__ __forceinline__ long long mem_quant(const SimDev& S, double v) {
   return __double_as_longlong(fma(v, 0x1p46, 0x1.8p52)) - __double_as_longlong(0x1.8p52);
 }
 
+template <bool kBig>
 __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restrict__ sims, Items it, int mode) {
-  __shared__ long long acc[3][kLdsNodes];
-  __shared__ double xs[3][kLdsNodes];  // the capsule's positions, read once
+  constexpr int kL = kBig ? 1 : kLdsNodes;
+  __shared__ long long acc[3][kL];
+  __shared__ double xs[3][kL];  // the capsule's positions, read once
   __shared__ double red[2][kMemThreads];
   const int tid = threadIdx.x;
   for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
@@ -640,23 +655,36 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
     if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     const int m = item - it.mesh_off[s];
     if (!mesh_has_terms(S, m)) continue;  // uniform
+    const int tm = S.mesh_tmpl[m];
+    const int nn = S.t_nn[tm], ne = S.t_ne[tm], nt = S.t_nt[tm];
+    if ((nn > kLdsNodes) != kBig) continue;  // the other variant's capsule
     const GLB double* mm = S.mesh_mem + 4 * (int64_t)m;
     const double kbtp = mm[0], kg = mm[1], kl = mm[2], kv = mm[3];
-    const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
-    const int nn = S.t_nn[tm], ne = S.t_ne[tm], nt = S.t_nt[tm];
     const int e0 = S.t_edge0[tm], tr0 = S.t_tri0[tm];
     const int64_t ms = (int64_t)S.maxn;
     const GLB double* X0 = S.X + off;
+    GLB unsigned long long* gacc = (GLB unsigned long long*)(S.Fext + off);  // kBig: [3][ms] from node off
+    auto pos = [&](int a, int i) -> double { return kBig ? X0[a * ms + i] : xs[a][i]; };
+    auto add = [&](int a, int i, long long v) {
+      if constexpr (kBig)
+        atomicAdd(gacc + a * ms + i, (unsigned long long)v);
+      else
+        fx_add(&acc[a][i], v);
+    };
     for (int i = tid; i < nn; i += kMemThreads) {
-      acc[0][i] = acc[1][i] = acc[2][i] = 0;
-      xs[0][i] = X0[i];
-      xs[1][i] = X0[ms + i];
-      xs[2][i] = X0[2 * ms + i];
+      if constexpr (kBig) {
+        gacc[i] = gacc[ms + i] = gacc[2 * ms + i] = 0ull;
+      } else {
+        acc[0][i] = acc[1][i] = acc[2][i] = 0;
+        xs[0][i] = X0[i];
+        xs[1][i] = X0[ms + i];
+        xs[2][i] = X0[2 * ms + i];
+      }
     }
-    __syncthreads();
+    __syncthreads();  // (kBig: the zeroed sums are in L2 before any atomic)
     const bool surf = kg != 0.0 || kl != 0.0 || kv != 0.0;
-    const D3 c = {xs[0][0], xs[1][0], xs[2][0]};
+    const D3 c = {pos(0, 0), pos(1, 0), pos(2, 0)};
     double cg = 0.0, cv = 0.0;
     if (surf) {  // uniform
       double As = 0.0, Vs = 0.0;
@@ -664,7 +692,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
         const GLB int* q = S.ttri + 3 * (int64_t)(tr0 + t);
         D3 p[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) p[k] = {xs[0][q[k]] - c.x, xs[1][q[k]] - c.y, xs[2][q[k]] - c.z};
+        for (int k = 0; k < 3; ++k) p[k] = {pos(0, q[k]) - c.x, pos(1, q[k]) - c.y, pos(2, q[k]) - c.z};
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         As += 0.5 * sqrt(dot(n, n));
         Vs += dot(p[0], cross(p[1], p[2]));  // 6 V_j
@@ -693,7 +721,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           v[k] = q[k];
-          p[k] = {xs[0][v[k]] - c.x, xs[1][v[k]] - c.y, xs[2][v[k]] - c.z};
+          p[k] = {pos(0, v[k]) - c.x, pos(1, v[k]) - c.y, pos(2, v[k]) - c.z};
         }
         const D3 n = cross(sub(p[1], p[0]), sub(p[2], p[0]));
         const double nl = sqrt(dot(n, n));
@@ -708,7 +736,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
           const D3 gV = cross(pn, pp);          // 6 dV_j/dp
           const double f[3] = {-(ca * gA.x + cv6 * gV.x), -(ca * gA.y + cv6 * gV.y), -(ca * gA.z + cv6 * gV.z)};
 #pragma unroll
-          for (int a = 0; a < 3; ++a) fx_add(&acc[a][v[k]], mem_quant(S, f[a]));
+          for (int a = 0; a < 3; ++a) add(a, v[k], mem_quant(S, f[a]));
         }
       }
     }
@@ -716,7 +744,7 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
       for (int e = tid; e < ne; e += kMemThreads) {
         const GLB int* ev = S.ev + 4 * (e0 + e);
         const int v1 = ev[1], v2 = ev[2];
-        const D3 d = {xs[0][v2] - xs[0][v1], xs[1][v2] - xs[1][v1], xs[2][v2] - xs[2][v1]};
+        const D3 d = {pos(0, v2) - pos(0, v1), pos(1, v2) - pos(1, v1), pos(2, v2) - pos(2, v1)};
         const double l = sqrt(dot(d, d)), l0 = S.el0[e0 + e];
         const double rl = 1.0 / l;
         const double x = 0.5 * l / l0;
@@ -732,15 +760,22 @@ __global__ __launch_bounds__(kMemThreads) void k_membrane(const SimDev* __restri
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const long long qf = mem_quant(S, f[a]);
-          fx_add(&acc[a][v1], qf);
-          fx_add(&acc[a][v2], -qf);
+          add(a, v1, qf);
+          add(a, v2, -qf);
         }
       }
     }
     __syncthreads();
     for (int i = tid; i < nn; i += kMemThreads) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) S.Fext[a * ms + off + i] = (double)acc[a][i] * 0x1p-46;
+      for (int a = 0; a < 3; ++a) {
+        long long q;
+        if constexpr (kBig)  // the atomics' results, from L2
+          q = (long long)__hip_atomic_load(gacc + a * ms + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        else
+          q = acc[a][i];
+        S.Fext[a * ms + off + i] = (double)q * 0x1p-46;
+      }
     }
     __syncthreads();  // accumulators read before the next capsule clears them
   }
@@ -763,6 +798,7 @@ __global__ __launch_bounds__(256) void k_edge_forces(const SimDev* __restrict__ 
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= it.sub) continue;
     const int m = mi - it.mesh_off[s];
+    if (S.mesh_rigid[m]) continue;  // uniform
     const int tm = S.mesh_tmpl[m];
     const int off = S.mesh_off[m];
     const double ks = S.mesh_ks[m], kb = S.mesh_kb[m];
@@ -806,6 +842,7 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
     const GLB double* scr = S.escr + 9 * (3 * (int64_t)off);
     const ListStep L = list_step(S, it, mode);
     clear_next_rebuild(S, L, c == 0 ? m : 1, mode);
+    if (S.mesh_rigid[m]) continue;  // a rigid body (k_rigid_nodes); uniform
     uint32_t fbits = 0u;
     for (int i0 = c * 256; i0 < nn; i0 += 256 * kNodeChunks) {
       const int i = i0 + tid;
@@ -838,6 +875,416 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
       else if (act) emit_node<R>(S, L, gid, Xp, F, mode, fbits);
     }
     flush_fmax(S, L.par, &wmax, fbits);
+  }
+}
+
+// -------------------------------------------------------- Morse repulsion --
+// Eq. (13) between the nodes of different capsules, before the force kernels
+// (which add the result to each node's membrane force):
+//   k_morse_bin    every capsule node into the neighbour grid of its step
+//                  parity (cells at least 2 lattice units wide, so every pair
+//                  closer than rc <= 2 lies in neighbouring cells); the
+//                  workgroups also empty the other parity's grid, used by the
+//                  previous step.
+//   k_morse_force  per node: the pair forces from the nodes of other capsules
+//                  in the 27 neighbouring cells, F = 2 alpha D0 (e^{-2 alpha
+//                  (r - r0)} - e^{-alpha (r - r0)}) (X_i - X_j) / r for r < rc,
+//                  each split into two 64-bit fixed-point words (units 2^-44
+//                  and 2^-96) and summed as integers: the sum is exact to
+//                  2^-96 per pair and does not depend on the order of the cell
+//                  lists, and the two nodes of a pair get exact opposites.
+//   k_morse_clear  an observation's grid, emptied after it (the next step
+//                  bins into the same parity).
+constexpr int kMorseThreads = 256;
+constexpr int kMorseChunks = 4;         // workgroups per capsule
+constexpr double kMorseHi = 0x1p44;     // unit of the high fixed-point word
+constexpr double kMorseLo = 0x1p52;     // unit of the low word, relative to the high one
+constexpr double kMorseLimit = 128.0;   // |pair force component| limit (health bit beyond)
+
+__device__ __forceinline__ int morse_axis(const SimDev& S, int a, double X) {
+  const int n = S.n[a], ng = S.ngm[a];
+  const double xw = S.wall[a] ? X : X - (double)n * floor(X / (double)n);
+  const int c = (int)floor(xw * (double)ng / (double)n);
+  return c < 0 ? 0 : (c >= ng ? ng - 1 : c);
+}
+
+__global__ __launch_bounds__(kMorseThreads) void k_morse_bin(const SimDev* __restrict__ sims, Items it, int mode) {
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total * kMorseChunks; item += gridDim.x) {
+    const int mi = item / kMorseChunks, c = item % kMorseChunks;
+    const int s = find_sim(it.mesh_off, it.nsim, mi);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    if (S.morse[0] == 0.0) continue;
+    const int m = mi - it.mesh_off[s];
+    const int par = (int)((*S.step + it.sub) & 1);
+    if (mode == 0) {
+      // empty the previous step's grid: this simulation's workgroups share it out
+      const int64_t nwg = (int64_t)(it.mesh_off[s + 1] - it.mesh_off[s]) * kMorseChunks;
+      const int64_t wg = (int64_t)m * kMorseChunks + c;
+      GLB int32_t* old = S.gcount + (int64_t)(par ^ 1) * S.ngrid;
+      for (int64_t k = wg * kMorseThreads + tid; k < S.ngrid; k += nwg * kMorseThreads) old[k] = 0;
+    }
+    if (S.mesh_rigid[m]) continue;  // uniform: bodies take no part
+    const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    for (int i = c * kMorseThreads + tid; i < nn; i += kMorseThreads * kMorseChunks) {
+      const int gid = off + i;
+      const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+      if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) continue;
+      const int64_t cell = morse_axis(S, 0, X[0]) +
+                           (int64_t)S.ngm[0] * (morse_axis(S, 1, X[1]) + (int64_t)S.ngm[1] * morse_axis(S, 2, X[2]));
+      const int64_t g = (int64_t)par * S.ngrid + cell;
+      const int pos = atomicAdd((int*)&S.gcount[g], 1);
+      if (pos < kMorseCap) S.glist[g * kMorseCap + pos] = gid;
+      else atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
+    }
+  }
+}
+
+// v added to the two-word accumulator: the whole multiples of 2^-44 (exact,
+// |v| 2^44 < 2^51), then the remainder (exact: a double minus its integer
+// part) rounded to a multiple of 2^-96.
+__device__ __forceinline__ void morse_accumulate(const SimDev& S, double v, long long& hi, long long& lo) {
+  if (!(fabs(v) < kMorseLimit)) {
+    atomicOr((unsigned*)S.health, (uint32_t)kHForceRange);
+    v = isnan(v) ? 0.0 : copysign(kMorseLimit, v);
+  }
+  const double t = v * kMorseHi;
+  const long long h = __double2ll_rz(t);
+  hi += h;
+  lo += __double2ll_rn((t - (double)h) * kMorseLo);
+}
+
+__global__ __launch_bounds__(kMorseThreads) void k_morse_force(const SimDev* __restrict__ sims, Items it, int mode) {
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total * kMorseChunks; item += gridDim.x) {
+    const int mi = item / kMorseChunks, c = item % kMorseChunks;
+    const int s = find_sim(it.mesh_off, it.nsim, mi);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    if (S.morse[0] == 0.0) continue;
+    const int m = mi - it.mesh_off[s];
+    if (S.mesh_rigid[m]) continue;
+    const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const int par = (int)((*S.step + it.sub) & 1);
+    const GLB int32_t* gc = S.gcount + (int64_t)par * S.ngrid;
+    const GLB int32_t* gl = S.glist + (int64_t)par * S.ngrid * kMorseCap;
+    const double D0 = S.morse[0], al = S.morse[1], r0 = S.morse[2], rc = S.morse[3];
+    for (int i = c * kMorseThreads + tid; i < nn; i += kMorseThreads * kMorseChunks) {
+      const int gid = off + i;
+      const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+      long long wh[3] = {0, 0, 0}, wl[3] = {0, 0, 0};  // two-word sums
+      if (isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2])) {
+        int lo[3], cnt[3];
+        for (int a = 0; a < 3; ++a) {
+          const int ca = morse_axis(S, a, X[a]), ng = S.ngm[a];
+          if (ng < 3) {
+            lo[a] = 0;  // every cell once
+            cnt[a] = ng;
+          } else if (S.wall[a]) {
+            lo[a] = ca > 0 ? ca - 1 : 0;
+            cnt[a] = (ca + 1 < ng ? ca + 1 : ng - 1) - lo[a] + 1;
+          } else {
+            lo[a] = ca - 1;  // wrapped below
+            cnt[a] = 3;
+          }
+        }
+        for (int kz = 0; kz < cnt[2]; ++kz)
+          for (int ky = 0; ky < cnt[1]; ++ky)
+            for (int kx = 0; kx < cnt[0]; ++kx) {
+              const int cx = wrap(lo[0] + kx, S.ngm[0]), cy = wrap(lo[1] + ky, S.ngm[1]),
+                        cz = wrap(lo[2] + kz, S.ngm[2]);
+              const int64_t cell = cx + (int64_t)S.ngm[0] * (cy + (int64_t)S.ngm[1] * cz);
+              int nc = gc[cell];
+              nc = nc < kMorseCap ? nc : kMorseCap;
+              for (int k = 0; k < nc; ++k) {
+                const int j = gl[cell * kMorseCap + k];
+                if (S.node_mesh[j] == m) continue;  // the same capsule
+                double d[3], r2 = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                  d[a] = X[a] - S.X[a * ms + j];
+                  if (!S.wall[a]) d[a] -= (double)S.n[a] * floor(d[a] / (double)S.n[a] + 0.5);
+                  r2 += d[a] * d[a];
+                }
+                const double r = sqrt(r2);
+                if (!(r < rc) || r == 0.0) continue;
+                const double e1 = exp(-al * (r - r0)), f = 2.0 * al * D0 * (e1 * e1 - e1) / r;
+                for (int a = 0; a < 3; ++a) morse_accumulate(S, f * d[a], wh[a], wl[a]);
+              }
+            }
+      }
+      for (int a = 0; a < 3; ++a) {
+        // carry the low word's whole multiples of 2^-44 into the high one;
+        // both words then convert exactly while |F| < 2^9
+        const long long c = wl[a] >> 52;
+        const long long h = wh[a] + c, l = wl[a] - (c << 52);
+        S.Fm[a * ms + gid] = (double)h / kMorseHi + (double)l / (kMorseHi * kMorseLo);
+      }
+    }
+  }
+}
+
+// an observation's grid emptied (over the simulation's grid cells)
+__global__ void k_morse_clear(const SimDev* __restrict__ sims, Items it) {
+  for (int s = 0; s < it.nsim; ++s) {
+    const SimDev& S = sims[s];
+    if (S.morse[0] == 0.0) continue;
+    GLB int32_t* g = S.gcount + (int64_t)(*S.step & 1) * S.ngrid;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.ngrid; k += (int64_t)gridDim.x * blockDim.x)
+      g[k] = 0;
+  }
+}
+
+// ------------------------------------------------------------ rigid bodies --
+// A rigid body (Sec. 2.3) is a mesh whose nodes move with one rigid motion:
+// X_k = xc + R(q) r_k, with node velocity U_k = v + Omega x (X_k - xc), Omega =
+// R Ib^-1 R^T L.  Each step:
+//  k_rigid_nodes  per node: the fluid velocity before the immersed-boundary
+//                 force, u* = (sum_i f_i c_i + g_body / 2) / rho (Eq. (3)
+//                 without the spread force), interpolated at X_k by Eq. (14)
+//                 from the populations themselves; the FSI force of Eq. (17),
+//                 rho_f (u* - U_k) / dt with rho_f = dt = 1, times the node's
+//                 weight dv_k (a third of its triangles' areas times one
+//                 lattice spacing).  The body receives it; the fluid receives
+//                 its opposite through the node's spreading record.
+//  k_rigid_body   per body: the force and torque, summed in a fixed order,
+//                 then Newton's second law with dt = 1 (semi-implicit Euler):
+//                 v += F / M, L += T, xc += v, the orientation turned by the
+//                 angle |Omega| about Omega (from the new L at the old
+//                 orientation), and the nodes placed at the new pose.
+constexpr int kRigidThreads = 256;
+constexpr int kRigidChunks = 4;  // workgroups per body in k_rigid_nodes
+
+__device__ __forceinline__ void quat_rot(const double q[4], double R[9]) {
+  const double w = q[0], x = q[1], y = q[2], z = q[3];
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - z * w);     R[2] = 2 * (x * z + y * w);
+  R[3] = 2 * (x * y + z * w);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - x * w);
+  R[6] = 2 * (x * z - y * w);     R[7] = 2 * (y * z + x * w);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// Omega = R Ib^-1 R^T L
+__device__ __forceinline__ void body_omega(const double R[9], const GLB double* ibinv, const double L[3],
+                                           double w[3]) {
+  double t[3], t2[3];
+  for (int a = 0; a < 3; ++a) t[a] = R[a] * L[0] + R[3 + a] * L[1] + R[6 + a] * L[2];
+  for (int a = 0; a < 3; ++a) t2[a] = ibinv[3 * a] * t[0] + ibinv[3 * a + 1] * t[1] + ibinv[3 * a + 2] * t[2];
+  for (int a = 0; a < 3; ++a) w[a] = R[3 * a] * t2[0] + R[3 * a + 1] * t2[1] + R[3 * a + 2] * t2[2];
+}
+
+// Fluid velocity without the immersed-boundary force, interpolated at X by
+// Eq. (14) (stencil base floor(X) - 1 .. + 2, the records' FP64 weights); a
+// solid stencil cell contributes its wall's velocity (the first wall axis
+// whose layer it is, as in the velocity field).
+template <int ST>
+__device__ void free_velocity(const SimDev& S, int par, const double X[3], double u[3]) {
+  using Rt = RealOf<ST>;
+  using T = typename Store<ST>::T;
+  double w[3][4];
+  int c[3][4];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double fb = floor(X[a]);
+    delta_weights(S.delta, X[a] - fb, w[a]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) c[a][k] = S.wall[a] ? (int)fb - 1 + k : wrap((int)fb - 1 + k, S.n[a]);
+  }
+  const GLB T* src = (const GLB T*)S.f[par];
+  u[0] = u[1] = u[2] = 0.0;
+  for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < 4; ++j)
+      for (int l = 0; l < 4; ++l) {
+        const int x = c[0][i], y = c[1][j], z = c[2][l];
+        const double ww = w[0][i] * w[1][j] * w[2][l];
+        double uc[3];
+        if (solid_cell(S, x, y, z)) {
+          const int cc[3] = {x, y, z};
+          int sa = -1;
+          for (int a = 0; a < 3; ++a)
+            if (sa < 0 && S.wall[a] && (cc[a] == 0 || cc[a] == S.n[a] - 1)) sa = a;
+          const double* uw = cc[sa] == 0 ? S.ulo[sa] : S.uhi[sa];
+          uc[0] = uw[0]; uc[1] = uw[1]; uc[2] = uw[2];
+        } else {
+          const int64_t cell = x + (int64_t)S.n[0] * (y + (int64_t)S.n[1] * z);
+          Rt h[kQ];
+          pull_cell<ST>(S, src, x, y, z, cell, h);
+          double dr = 0.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+          for (int q = 0; q < kQ; ++q) {
+            const double hq = (double)h[q];
+            dr += hq;
+            if (kCx[q]) j[0] += kCx[q] > 0 ? hq : -hq;
+            if (kCy[q]) j[1] += kCy[q] > 0 ? hq : -hq;
+            if (kCz[q]) j[2] += kCz[q] > 0 ? hq : -hq;
+          }
+          for (int a = 0; a < 3; ++a) uc[a] = (j[a] + 0.5 * S.gb[a]) / (1.0 + dr);
+        }
+        for (int a = 0; a < 3; ++a) u[a] += ww * uc[a];
+      }
+}
+
+template <int ST>
+__global__ __launch_bounds__(kRigidThreads) void k_rigid_nodes(const SimDev* __restrict__ sims, Items it, int mode) {
+  using R = RealOf<ST>;
+  __shared__ BinTable bt;
+  __shared__ uint32_t wmax;
+  const int tid = threadIdx.x;
+  if (tid == 0) wmax = 0u;
+  for (int item = xcd_block(); item < it.mesh_total * kRigidChunks; item += gridDim.x) {
+    const int mi = item / kRigidChunks, c = item % kRigidChunks;
+    const int s = find_sim(it.mesh_off, it.nsim, mi);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    const int m = mi - it.mesh_off[s];
+    if (!S.mesh_rigid[m]) continue;  // uniform
+    const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    const ListStep L = list_step(S, it, mode);
+    const int par = (int)((*S.step + it.sub) & 1);
+    const GLB double* bs = S.bstate + kBodyState * (int64_t)m;
+    const double xc[3] = {bs[0], bs[1], bs[2]}, q[4] = {bs[3], bs[4], bs[5], bs[6]};
+    const double v[3] = {bs[7], bs[8], bs[9]}, Lm[3] = {bs[10], bs[11], bs[12]};
+    double Rm[9], w[3];
+    quat_rot(q, Rm);
+    body_omega(Rm, S.bconst + kBodyConst * (int64_t)m + 1, Lm, w);
+    uint32_t fbits = 0u;
+    for (int i0 = c * kRigidThreads; i0 < nn; i0 += kRigidThreads * kRigidChunks) {  // uniform
+      const int i = i0 + tid;
+      const bool act = i < nn;
+      const int gid = off + i;
+      double Xp[3] = {0.0, 0.0, 0.0}, Fv[3] = {0.0, 0.0, 0.0};
+      if (act) {
+        bool inside = true;
+        for (int a = 0; a < 3; ++a) {
+          Xp[a] = S.X[a * ms + gid];
+          inside &= isfinite(Xp[a]) && (!S.wall[a] || (Xp[a] >= 1.0 && Xp[a] < (double)(S.n[a] - 2)));
+        }
+        const double r[3] = {Xp[0] - xc[0], Xp[1] - xc[1], Xp[2] - xc[2]};
+        const double U[3] = {v[0] + w[1] * r[2] - w[2] * r[1], v[1] + w[2] * r[0] - w[0] * r[2],
+                             v[2] + w[0] * r[1] - w[1] * r[0]};
+        double us[3] = {U[0], U[1], U[2]};  // a node out of range exerts no force
+        if (inside) free_velocity<ST>(S, par, Xp, us);
+        const double dv = S.ndv[gid];
+        double fb[3];
+        for (int a = 0; a < 3; ++a) {
+          fb[a] = dv * (us[a] - U[a]);  // on the body, Eq. (17)
+          Fv[a] = -fb[a];               // on the fluid
+          S.Fext[a * ms + gid] = fb[a];
+          if (mode == 1) S.U[a * ms + gid] = U[a];
+        }
+        GLB double* tq = S.escr + 3 * (int64_t)gid;  // the node's torque about xc
+        tq[0] = r[1] * fb[2] - r[2] * fb[1];
+        tq[1] = r[2] * fb[0] - r[0] * fb[2];
+        tq[2] = r[0] * fb[1] - r[1] * fb[0];
+      }
+      if (S.skin == 0) emit_nodes<R>(S, bt, L, act, gid, Xp, Fv, mode, fbits, 2);  // uniform: barriers
+      else if (act) emit_node<R>(S, L, gid, Xp, Fv, mode, fbits, 2);
+    }
+    flush_fmax(S, L.par, &wmax, fbits);
+  }
+}
+
+__global__ __launch_bounds__(kRigidThreads) void k_rigid_body(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ double red[6][kRigidThreads];
+  __shared__ double pose[12];  // the new xc[3], R[9]
+  const int tid = threadIdx.x;
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
+    const SimDev& S = sims[s];
+    if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
+    const int m = item - it.mesh_off[s];
+    if (!S.mesh_rigid[m]) continue;  // uniform
+    const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
+    const int64_t ms = (int64_t)S.maxn;
+    // force and torque: per-thread sums in node order, then a fixed tree
+    double acc[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int i = tid; i < nn; i += kRigidThreads) {
+      const int gid = off + i;
+      for (int a = 0; a < 3; ++a) {
+        acc[a] += S.Fext[a * ms + gid];
+        acc[3 + a] += S.escr[3 * (int64_t)gid + a];
+      }
+    }
+    for (int a = 0; a < 6; ++a) red[a][tid] = acc[a];
+    __syncthreads();
+    for (int o = kRigidThreads / 2; o > 0; o >>= 1) {
+      if (tid < o)
+        for (int a = 0; a < 6; ++a) red[a][tid] += red[a][tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      GLB double* ft = S.bft + 6 * (int64_t)m;
+      for (int a = 0; a < 6; ++a) ft[a] = red[a][0];
+      if (mode == 0) {
+        GLB double* bs = S.bstate + kBodyState * (int64_t)m;
+        const GLB double* bc = S.bconst + kBodyConst * (int64_t)m;
+        double xc[3], q[4], v[3], Lm[3], Rm[9], w[3];
+        for (int a = 0; a < 3; ++a) {
+          v[a] = bs[7 + a] + red[a][0] / bc[0];
+          Lm[a] = bs[10 + a] + red[3 + a][0];
+          xc[a] = bs[a] + v[a];
+        }
+        for (int a = 0; a < 4; ++a) q[a] = bs[3 + a];
+        quat_rot(q, Rm);
+        body_omega(Rm, bc + 1, Lm, w);
+        const double th = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+        if (th > 0.0) {
+          double sh, ch;
+          sincos(0.5 * th, &sh, &ch);
+          const double k = sh / th, d[4] = {ch, w[0] * k, w[1] * k, w[2] * k};
+          const double n4[4] = {d[0] * q[0] - d[1] * q[1] - d[2] * q[2] - d[3] * q[3],
+                                d[0] * q[1] + d[1] * q[0] + d[2] * q[3] - d[3] * q[2],
+                                d[0] * q[2] - d[1] * q[3] + d[2] * q[0] + d[3] * q[1],
+                                d[0] * q[3] + d[1] * q[2] - d[2] * q[1] + d[3] * q[0]};
+          const double nq = sqrt(n4[0] * n4[0] + n4[1] * n4[1] + n4[2] * n4[2] + n4[3] * n4[3]);
+          for (int a = 0; a < 4; ++a) q[a] = n4[a] / nq;
+          quat_rot(q, Rm);
+        }
+        for (int a = 0; a < 3; ++a) {
+          bs[a] = xc[a];
+          bs[7 + a] = v[a];
+          bs[10 + a] = Lm[a];
+          pose[a] = xc[a];
+        }
+        for (int a = 0; a < 4; ++a) bs[3 + a] = q[a];
+        for (int a = 0; a < 9; ++a) pose[3 + a] = Rm[a];
+      }
+    }
+    __syncthreads();
+    if (mode == 0) {
+      // the nodes at the new pose; with a skin, a node whose stencil base left
+      // its skin raises the next step's rebuild flag
+      const int next_par = (int)((*S.step + it.sub + 1) & 1);
+      bool out = false;
+      for (int i = tid; i < nn; i += kRigidThreads) {
+        const int gid = off + i;
+        double xn[3];
+        for (int a = 0; a < 3; ++a) {
+          const double r0 = S.Xr[gid], r1 = S.Xr[ms + gid], r2 = S.Xr[2 * ms + gid];
+          xn[a] = pose[a] + pose[3 + 3 * a] * r0 + pose[4 + 3 * a] * r1 + pose[5 + 3 * a] * r2;
+          S.X[a * ms + gid] = xn[a];
+        }
+        if (S.skin) {
+          const GLB int16_t* b0 = S.bb0 + 4 * (int64_t)gid;
+          for (int a = 0; a < 3; ++a) {
+            const double fb = floor(xn[a]);
+            if (!(fabs(fb) < 1e9)) {
+              out = true;
+              continue;
+            }
+            int dlt = (int)fb - b0[a];
+            if (!S.wall[a]) {
+              dlt %= S.n[a];
+              dlt = dlt > S.n[a] / 2 ? dlt - S.n[a] : (dlt < -S.n[a] / 2 ? dlt + S.n[a] : dlt);
+            }
+            out |= dlt > S.skin || dlt < -S.skin;
+          }
+        }
+      }
+      if (out) atomicOr((unsigned*)&S.lctl[2 + next_par], 1u);
+    }
+    __syncthreads();  // red and pose are reused by the next body
   }
 }
 
@@ -1023,12 +1470,30 @@ int grid_for(int items, int cap) {
   return (g + kXcds - 1) / kXcds * kXcds;
 }
 
-template <typename R>
+template <int ST>
 void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
+  using R = RealOf<ST>;
   if (it.mesh_total <= 0) return;
-  if (it.membrane)
-    hipLaunchKernelGGL(k_membrane, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kMemThreads), 0, s, sims, it,
+  if (it.membrane) {
+    hipLaunchKernelGGL(k_membrane<false>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kMemThreads), 0, s, sims,
+                       it, mode);
+    if (it.big_templates)
+      hipLaunchKernelGGL(k_membrane<true>, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kMemThreads), 0, s, sims,
+                         it, mode);
+  }
+  if (it.morse) {
+    const dim3 grid(grid_for(it.mesh_total * kMorseChunks, 1 << 20));
+    hipLaunchKernelGGL(k_morse_bin, grid, dim3(kMorseThreads), 0, s, sims, it, mode);
+    hipLaunchKernelGGL(k_morse_force, grid, dim3(kMorseThreads), 0, s, sims, it, mode);
+    if (mode == 1) hipLaunchKernelGGL(k_morse_clear, dim3(256), dim3(256), 0, s, sims, it);
+  }
+  if (it.rigid) {
+    // bodies first: their kernels only read positions and write their own nodes
+    hipLaunchKernelGGL(k_rigid_nodes<ST>, dim3(grid_for(it.mesh_total * kRigidChunks, 1 << 20)),
+                       dim3(kRigidThreads), 0, s, sims, it, mode);
+    hipLaunchKernelGGL(k_rigid_body, dim3(grid_for(it.mesh_total, 1 << 16)), dim3(kRigidThreads), 0, s, sims, it,
                        mode);
+  }
   if (it.big_templates || it.forces_variant == 1) {
     hipLaunchKernelGGL(k_edge_forces, dim3(grid_for(it.mesh_total * kEdgeChunks, 1 << 20)), dim3(256), 0, s,
                        sims, it, mode);
@@ -1046,8 +1511,9 @@ void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
 }  // namespace
 
 void launch_forces(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {
-  if (storage == kF64) forces_impl<double>(sims, it, mode, s);
-  else forces_impl<float>(sims, it, mode, s);
+  if (storage == kF64) forces_impl<kF64>(sims, it, mode, s);
+  else if (storage == kF32) forces_impl<kF32>(sims, it, mode, s);
+  else forces_impl<kF16>(sims, it, mode, s);
 }
 
 void launch_interp(int storage, const SimDev* sims, const Items& it, int mode, hipStream_t s) {

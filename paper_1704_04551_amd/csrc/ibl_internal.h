@@ -38,6 +38,9 @@ constexpr int kLdsNodes = 642;       // template size handled by the LDS force k
 constexpr int kLdsEdges = 1920;
 constexpr int kReduceItemCells = 4096;
 constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup per mesh)
+constexpr int kBodyState = 16;   // doubles per rigid-body state record
+constexpr int kBodyConst = 10;   // doubles per rigid-body constants record
+constexpr int kMorseCap = 48;    // nodes per cell of the Morse neighbour grid
 
 // ------------------------------------------------------------------------
 // D3Q19 in the library's order: the rest velocity, the z = 0 plane, then the
@@ -80,7 +83,8 @@ enum Health : uint32_t {
 template <typename R>
 struct alignas(16) NodeRec {
   int32_t base[3];   // floor(X) per axis (periodic axes: modulo n)
-  int32_t valid;     // 0 when the node is outside the admissible range
+  int32_t valid;     // 0 when the node is outside the admissible range, 1 a capsule's
+                     // node (interpolated and moved), 2 a rigid body's node (spread only)
   R w[3][4];         // phi at offsets -1, 0, +1, +2 from base, per axis
   R F[3];            // membrane force
   R pad;
@@ -88,7 +92,7 @@ struct alignas(16) NodeRec {
 template <>
 struct alignas(16) NodeRec<float> {
   int16_t base[3];   // floor(X) per axis (periodic axes: modulo n); axes < 2^15 cells
-  int16_t valid;
+  int16_t valid;     // as above
   float d[3];        // X - base per axis, in [0, 1)
   float F[3];
 };
@@ -108,6 +112,9 @@ struct SimDev {
   int32_t nq[3];          // home cubes per axis
   int64_t ncube;
   double tau;
+  // collision coefficients (see k_lattice): om = 1/tau, pre = 1 - 1/(2 tau),
+  // then 1 - om, 3 om, 9/2 om, 3 pre, 9 pre
+  double om, pre, om1, a0, a1, b0, b1;
   double gb[3];
   double ulo[3][3];
   double uhi[3][3];
@@ -142,7 +149,23 @@ struct SimDev {
   IBL_G(double) mesh_ks;
   IBL_G(double) mesh_kb;
   IBL_G(double) mesh_mem;       // [max_meshes][4] kBT/p, kg, kl, kv (zero: term absent)
-  IBL_G(double) Fext;           // [3][max_nodes] force of those terms (k_membrane)
+  IBL_G(double) Fext;           // [3][max_nodes] force of those terms (k_membrane); for a
+                                //     rigid body's nodes, their FSI force on the body
+  // rigid bodies (Sec. 2.3, Eq. (17)): a mesh flagged rigid moves as one body
+  IBL_G(int32_t) mesh_rigid;    // [max_meshes] 1: rigid body, 0: deformable capsule
+  IBL_G(double) bstate;         // [max_meshes][16] xc[3], q[4] (w, x, y, z), v[3], L[3] (lab frame)
+  IBL_G(double) bconst;         // [max_meshes][10] mass, inverse body-frame inertia tensor [9]
+  IBL_G(double) bft;            // [max_meshes][6] force and torque on the body, last evaluation
+  IBL_G(double) Xr;             // [3][max_nodes] body-frame node offsets from the centre of mass
+  IBL_G(double) ndv;            // [max_nodes] node weight: a third of its triangles' areas x 1 lu
+  IBL_G(int32_t) node_mesh;     // [max_nodes] mesh of each node
+  // inter-capsule Morse repulsion (Eq. (13)): neighbour grid by step parity
+  double morse[4];              // D0, alpha, r0, rc (D0 = 0: off)
+  int32_t ngm[3];               // grid cells per axis (each at least 2 lattice units wide)
+  int64_t ngrid;
+  IBL_G(int32_t) gcount;        // [2][ngrid] nodes per grid cell
+  IBL_G(int32_t) glist;         // [2][ngrid][kMorseCap] node ids
+  IBL_G(double) Fm;             // [3][max_nodes] Morse force of the step
   // templates
   IBL_G(int32_t) t_nn;          // [max_templates]
   IBL_G(int32_t) t_node0;       // first template-node index
@@ -178,6 +201,9 @@ struct Items {
   int32_t forces_variant;    // 0: one LDS workgroup per capsule, 1: split edge / node kernels,
                              // 2: FP32 / FP16 storage through the edge-share LDS kernel
   int32_t membrane;          // 1 when some mesh has WLC-POW, area or volume terms
+  int32_t moving_walls;      // 1 when some simulation has a wall layer with a non-zero velocity
+  int32_t rigid;             // 1 when some mesh is a rigid body
+  int32_t morse;             // 1 when some simulation has the Morse repulsion on
   const int32_t* lat_off;    // [nsim + 1]
   const int32_t* red_off;
   const int32_t* mesh_off;

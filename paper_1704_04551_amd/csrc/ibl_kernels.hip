@@ -16,64 +16,38 @@
 // serves a single simulation or a batch of uneven ones.
 #include <type_traits>
 
+// No implicit contraction of a * b + c into an FMA anywhere in this file:
+// the compiler may contract differently in different instantiations of a
+// kernel (with and without moving walls, say), and results that must be
+// bitwise equal across them would then differ in the last bit.  The FMAs of
+// the hot paths are written out.
+#pragma clang fp contract(off)
+
 #include "ibl_device.h"
 
 namespace ibl {
 namespace {
 
-// -------------------------------------------------------------- streaming --
-// The populations are stored post-collision (f* of the previous step) and
-// streamed on read ("pull"): f_q(x) = f*_q(x - c_q).  Where x - c_q is a wall
-// layer, halfway bounce-back returns the cell's own opposite population with
-// the moving-wall term: f_q(x) = f*_opp(q)(x) + 6 w_q (c_q . u_wall), u_wall
-// the velocity of the first wall axis (x, y, z order) whose layer x - c_q is.
-// Writes are aligned (each cell writes its own populations); only the reads
-// are shifted.
-
-// Source of direction q for fluid cell (x, y, z): the element index of the
-// value to read, and the bounce-back wall layer (2 * axis + [hi side]) or -1.
-// Cell indices fit in 32 bits (the descriptor check bounds the lattice).
-__device__ __forceinline__ int pull_source(const SimDev& S, int q, int x, int y, int z, int cell, int& layer) {
-  const int nx = S.n[0], ny = S.n[1], nz = S.n[2];
-  const int xs = x - kCx[q], ys = y - kCy[q], zs = z - kCz[q];
-  const int sy = nx, sz = nx * ny;
-  int sc = cell - kCx[q] - sy * kCy[q] - sz * kCz[q];
-  // periodic wrap: one axis length in index units (nx, nx ny, nx ny nz)
-  if (kCx[q] && !S.wall[0]) sc += xs < 0 ? nx : (xs >= nx ? -nx : 0);
-  if (kCy[q] && !S.wall[1]) sc += ys < 0 ? sz : (ys >= ny ? -sz : 0);
-  if (kCz[q] && !S.wall[2]) sc += zs < 0 ? (int)S.ncell : (zs >= nz ? -(int)S.ncell : 0);
-  const bool bx = kCx[q] && S.wall[0] && (xs == 0 || xs == nx - 1);
-  const bool by = kCy[q] && S.wall[1] && (ys == 0 || ys == ny - 1);
-  const bool bz = kCz[q] && S.wall[2] && (zs == 0 || zs == nz - 1);
-  layer = bx ? (xs != 0) : (by ? 2 + (ys != 0) : (bz ? 4 + (zs != 0) : -1));
-  return layer >= 0 ? cell : sc;
+// 1 / r for r near 1: hardware reciprocal, refined by Newton steps to the
+// type's precision
+__device__ __forceinline__ float rcp_r(float r) {
+  const float i = __builtin_amdgcn_rcpf(r);
+  return fmaf(i, fmaf(-r, i, 1.0f), i);
+}
+__device__ __forceinline__ double rcp_r(double r) {
+  double i = __builtin_amdgcn_rcp(r);
+  i = fma(i, fma(-r, i, 1.0), i);
+  return fma(i, fma(-r, i, 1.0), i);
 }
 
-template <int ST>
-__device__ __forceinline__ void pull_cell(const SimDev& S, const GLB typename Store<ST>::T* src, int x, int y,
-                                          int z, int64_t cell, RealOf<ST> h[kQ]) {
-  using R = RealOf<ST>;
-  using T = typename Store<ST>::T;
-  const int64_t nc = S.ncell;
-  // branch-free addresses, so the 19 loads issue together.  Each load is a
-  // uniform base (population min(q, opp q)) plus a 32-bit byte offset: the
-  // descriptor check keeps 2 ncell elements below 2^32 bytes.
-#pragma unroll
-  for (int q = 0; q < kQ; ++q) {
-    int layer;
-    const int sc = pull_source(S, q, x, y, z, (int)cell, layer);
-    const int plo = q < opp(q) ? q : opp(q);
-    const uint32_t el = (uint32_t)(((layer >= 0 ? opp(q) : q) - plo) * (int)nc + sc);
-    const GLB char* base = (const GLB char*)(src + (int64_t)plo * nc);
-    h[q] = Store<ST>::h((const GLB T*)(base + el * (uint32_t)sizeof(T)), 0, q);
-  }
-  // moving-wall term of the bounce-back links
-#pragma unroll
-  for (int q = 1; q < kQ; ++q) {
-    int layer;
-    (void)pull_source(S, q, x, y, z, (int)cell, layer);
-    if (layer >= 0) h[q] += (R)S.bbw[q][layer];
-  }
+// Wall term carried by the stored slot q of fluid cell (x, y, z): where
+// x + c_q is a wall layer, the slot is read back by the cell's own
+// bounce-back of direction opp(q), which adds 6 w_opp(q) (c_opp(q) . u_wall);
+// elsewhere 0.
+__device__ __forceinline__ double slot_wall_term(const SimDev& S, int q, int x, int y, int z, int cell) {
+  int layer;
+  (void)pull_source(S, opp(q), x, y, z, cell, layer);
+  return layer >= 0 ? S.bbw[opp(q)][layer] : 0.0;
 }
 
 // ------------------------------------------------------------------ init --
@@ -132,7 +106,8 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
   u[2 * S.ncell + cell] = (R)u0[2];
   // stored populations are post-collision values that the first step's
   // pull turns into f_eq(1, u0): the one read by the consumer x + c_q, or,
-  // where x + c_q is a wall layer, the bounce-back source of x itself
+  // where x + c_q is a wall layer, the bounce-back value of direction opp(q)
+  // at x itself (the slot carries its wall term, as the collision stores it)
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     int cn[3] = {x + kCx[q], y + kCy[q], z + kCz[q]};
@@ -143,8 +118,7 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
     }
     double hq;
     if (q != 0 && wall_axis >= 0) {
-      const double* uw = cn[wall_axis] == 0 ? S.ulo[wall_axis] : S.uhi[wall_axis];
-      hq = h_eq(opp(q), u0) + 6.0 * wq(q) * (kCx[q] * uw[0] + kCy[q] * uw[1] + kCz[q] * uw[2]);
+      hq = h_eq(opp(q), u0);
     } else {
       double uc[3];
       u_init(cn, uc);
@@ -165,6 +139,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     const int64_t b = item - it.lat_off[s];
     // the arena may hold a previous user's data: every list is emptied
     for (int64_t j = b * kBrickThreads + tid; j < S.ncube; j += S.nbrick * kBrickThreads) S.hcount[j] = 0;
+    for (int64_t j = b * kBrickThreads + tid; j < 2 * S.ngrid; j += S.nbrick * kBrickThreads) S.gcount[j] = 0;
     if (tid == 0) {
       S.bcount[b] = 0;
       S.bcount[S.nbrick + b] = 0;
@@ -183,8 +158,9 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
   }
 }
 
-// Candidate lists emptied and marked for a rebuild at the next step (after
-// the nodes or the step counter were set from the host).
+// Candidate lists and the Morse neighbour grids emptied, lists marked for a
+// rebuild at the next step (after the nodes or the step counter were set
+// from the host).
 __global__ void k_reset_lists(const SimDev* __restrict__ sim) {
   const SimDev& S = *sim;
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -192,6 +168,7 @@ __global__ void k_reset_lists(const SimDev* __restrict__ sim) {
     S.bcount[b] = 0;
     S.bcount[S.nbrick + b] = 0;
   }
+  for (int64_t k = b; k < 2 * S.ngrid; k += (int64_t)gridDim.x * blockDim.x) S.gcount[k] = 0;
   if (b == 0) reset_list_control(S);
 }
 
@@ -307,14 +284,20 @@ struct FixAcc<double> {
   }
 };
 
-// FP32 / FP16: registers capped for 5 waves per SIMD (measured best: the
-// spreading phase of one brick hides behind the streaming of the others; FP16
-// spills one register under the cap and still gains)
-template <int ST>
-__global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(const SimDev* __restrict__ sims,
+// FP32 / FP16: registers capped for kLatticeWaves waves per SIMD (the
+// spreading phase of one brick hides behind the streaming of the others)
+#ifndef IBL_LATTICE_WAVES
+#define IBL_LATTICE_WAVES 5
+#endif
+constexpr int kLatticeWaves = IBL_LATTICE_WAVES;
+// MW: some simulation of the launch set has a moving wall (the stored
+// bounce-back slots carry a wall term; without moving walls every term is 0).
+template <int ST, bool MW>
+__global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
   using R = RealOf<ST>;
+  using D = typename Store<ST>::D;  // type of the collision's O(u) part
   using FA = typename std::conditional<ST == kF16, FixAcc3, FixAcc<R>>::type;
   constexpr int BZ = brick_depth(ST);
   static_assert(FA::kCells == kBrickThreads * BZ, "spread-force field of one brick");
@@ -376,11 +359,12 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
       inv = (R)ldexp(1.0, -sh);
       for (int i = tid; i < cnt; i += kBrickThreads) {
         if (i != tid) q = *(const NodeRec<R>*)(rec + list[i]);
-        // a node is interpolated through its home cube's list (one entry per
-        // node); a node that is no longer valid is neither spread nor moved
+        // a capsule's node is interpolated through its home cube's list (one
+        // entry per node); a rigid body's node is spread only (its body moves
+        // it); a node that is no longer valid is neither spread nor moved
         const bool val = q.valid != 0;
         uint16_t hrank = 0xffffu;
-        if (val && (unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
+        if (q.valid == 1 && (unsigned)(q.base[0] - ox) < (unsigned)bx && (unsigned)(q.base[1] - oy) < (unsigned)by &&
             (unsigned)(q.base[2] - oz) < (unsigned)bz) {
           const int lc = (q.base[0] >> kCubeShift[0]) - (ox >> kCubeShift[0]) +
                          nlx * ((q.base[1] >> kCubeShift[1]) - (oy >> kCubeShift[1]));
@@ -439,14 +423,13 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
     }
     // ---- collide-stream, a column of BZ cells per thread
     const int x = ox + (tid & (bx - 1)), y = oy + (tid >> S.bsh[0]);
+    uint32_t bad = 0u;  // health bits of this thread's cells
     if (x < nx && y < ny) {
       const int64_t nc = S.ncell;
       const uint32_t salt = (uint32_t)stepn * 0x85EBCA77u + 0x165667B1u;
       const GLB T* src = (const GLB T*)S.f[par];
       GLB T* dst = (GLB T*)S.f[par ^ 1];
       GLB R* uf = (GLB R*)S.u;  // [3][ncell]
-      const R om = (R)(1.0 / S.tau);
-      const R pre = (R)(1.0 - 0.5 / S.tau);
 #pragma unroll 1
       for (int k = 0; k < BZ; ++k) {
         const int z = oz + k;
@@ -463,25 +446,32 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
         }
         R h[kQ];
         pull_cell<ST>(S, src, x, y, z, cell, h);
-        // moments, Eq. (3): rho = sum f = 1 + sum h ; rho u = sum h c + g/2
-        R drho = (R)0, jx = (R)0, jy = (R)0, jz = (R)0;
+        // moments, Eq. (3), in type D (FP64 for FP64 / FP32 storage: exact sums
+        // of the stored values): rho = sum f = 1 + sum h ; J = rho u = sum h c + g/2
+        D drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
-          drho += h[q];
-          if (kCx[q]) jx += kCx[q] > 0 ? h[q] : -h[q];
-          if (kCy[q]) jy += kCy[q] > 0 ? h[q] : -h[q];
-          if (kCz[q]) jz += kCz[q] > 0 ? h[q] : -h[q];
+          const D hq = (D)h[q];
+          drho += hq;
+          if (kCx[q]) jx += kCx[q] > 0 ? hq : -hq;
+          if (kCy[q]) jy += kCy[q] > 0 ? hq : -hq;
+          if (kCz[q]) jz += kCz[q] > 0 ? hq : -hq;
         }
         R gix = (R)0, giy = (R)0, giz = (R)0;  // spread force g_IB
         if (ib) FA::get(gq, li, inv, gix, giy, giz);
-        const R gx = (R)S.gb[0] + gix, gy = (R)S.gb[1] + giy, gz = (R)S.gb[2] + giz;
-        const R rho = (R)1 + drho;
-        const R irho = (R)1 / rho;
-        const R ux = (jx + (R)0.5 * gx) * irho;
-        const R uy = (jy + (R)0.5 * gy) * irho;
-        const R uz = (jz + (R)0.5 * gz) * irho;
+        const D gx = (D)S.gb[0] + (D)gix, gy = (D)S.gb[1] + (D)giy, gz = (D)S.gb[2] + (D)giz;
+        const D Jx = fma((D)0.5, gx, jx), Jy = fma((D)0.5, gy, jy), Jz = fma((D)0.5, gz, jz);
+        const D rho = (D)1 + drho;
+        // velocity in the compute type R (FP32, or FP64 for FP64 storage)
+        const R rr = (R)rho;
+        const R ir = rcp_r(rr);
+        const R ux = (R)Jx * ir, uy = (R)Jy * ir, uz = (R)Jz * ir;
+        const R usq = fma(uz, uz, fma(uy, uy, ux * ux));
+        // health, per cell: non-finite populations, rho <= 0, |u| > 0.3
+        bad |= !isfinite(drho) ? (uint32_t)kHNonfiniteF
+                               : (!(rho > (D)0) ? (uint32_t)kHRho : (!(usq <= (R)0.09) ? (uint32_t)kHMach : 0u));
         if (mode == 1) {
-          ((GLB R*)S.rho)[cell] = rho;
+          ((GLB R*)S.rho)[cell] = rr;
           uf[cell] = ux;
           uf[nc + cell] = uy;
           uf[2 * nc + cell] = uz;
@@ -496,26 +486,65 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : 5) void k_lattice(c
           uf[nc + cell] = uy;
           uf[2 * nc + cell] = uz;
         }
-        // per-(cell, step) random bits for stochastic rounding (FP16 storage)
-        uint32_t csalt = (uint32_t)cell * 0x9E3779B1u + salt;
-        csalt ^= csalt >> 15;
-        csalt *= 0x2c1b3c6du;
-        csalt ^= csalt >> 12;
-        // collision, Eq. (1), (2), (4), in offset form h = f - w
-        const R usq = ux * ux + uy * uy + uz * uz;
-        const R ug = ux * gx + uy * gy + uz * gz;
+        // BGK collision toward f_eq of Eq. (2) with the forcing term of Eq. (4),
+        // in offset form, h* = (1 - om) h + om (f_eq - w) + F, split by size:
+        //   L_q = (1 - om) h_q + om w_q (drho + 3 c_q . J)                 (type D)
+        //   N_q = w_q [om rho (9/2 (c_q . u)^2 - 3/2 u^2)
+        //              + pre (3 (c_q . g - u . g) + 9 (c_q . u)(c_q . g))]  (type R)
+        // For FP32 storage L is FP64: it carries the O(1e-3) part, whose FP32
+        // rounding would recur every step in a steady flow and bias it; N is
+        // O(u^2, g), where FP32 rounding is far below FP32 storage.  FP16
+        // storage computes both in FP32 (its stochastic rounding noise is four
+        // orders above that bias), FP64 storage both in FP64.
+        // Directions 2k-1 and 2k are opposite (c -> -c): N's even part
+        // w_q [(c.u)(9/2 om rho (c.u) + 9 pre (c.g)) + C0] is shared and its odd
+        // part 3 pre w_q (c.g) changes sign, as does L's 3 om w_q c.J.
+        const R gxr = (R)gx, gyr = (R)gy, gzr = (R)gz;
+        const R omr = (R)S.om * rr, prer = (R)S.pre;
+        const R k45 = (R)4.5 * omr, k9 = (R)9 * prer, k3 = (R)3 * prer;
+        const R C0 = -fma((R)1.5 * omr, usq, k3 * fma(uz, gzr, fma(uy, gyr, ux * gxr)));
+        const D omd = (D)S.om * drho, om3 = (D)S.a0, om1 = (D)S.om1;
+        // random bits of the stochastic rounding: a hash of (cell, step), then
+        // one xorshift step per pair of directions (16 bits each)
+        uint32_t rs = (uint32_t)cell * 0x9E3779B1u + salt;
+        rs ^= rs >> 16;  // integer finaliser of the "lowbias32" family (Wellons)
+        rs *= 0x7feb352du;
+        rs ^= rs >> 15;
+        rs *= 0x846ca68bu;
+        rs ^= rs >> 16;
+        rs |= 1u;  // a non-zero xorshift state
+        // uniform plane base plus a 32-bit byte offset (as for the loads)
+        auto store = [&](int q, D v, uint32_t r16) {
+          GLB T* at = (GLB T*)((GLB char*)(dst + (int64_t)q * nc) + (uint32_t)cell * (uint32_t)sizeof(T));
+          if constexpr (MW) v += (D)slot_wall_term(S, q, x, y, z, (int)cell);
+          Store<ST>::put_sr(at, v, r16);
+        };
+        store(0, fma(om1, (D)h[0], (D)wq(0) * omd + (D)((R)wq(0) * C0)), rs);
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-          const R w = (R)wq(q);
-          const R cu = (R)kCx[q] * ux + (R)kCy[q] * uy + (R)kCz[q] * uz;
-          const R cg = (R)kCx[q] * gx + (R)kCy[q] * gy + (R)kCz[q] * gz;
-          // f_eq - w = w (drho + rho (3 cu + 9/2 cu^2 - 3/2 u^2))
-          const R heq = w * (drho + rho * ((R)3 * cu + (R)4.5 * cu * cu - (R)1.5 * usq));
-          const R Fq = pre * w * ((R)3 * (cg - ug) + (R)9 * cu * cg);
-          // post-collision value, stored in place; the next step pulls it
-          Store<ST>::put_sr(dst, (int64_t)q * nc + cell, h[q] - om * (h[q] - heq) + Fq, csalt, q);
+        for (int q = 1; q < kQ; q += 2) {
+          // c_q . v for c_q with components in {-1, 0, 1}: sums and differences only
+          auto cdot = [q](auto vx, auto vy, auto vz) {
+            decltype(vx) d = 0;
+            if (kCx[q]) d = kCx[q] > 0 ? vx : -vx;
+            if (kCy[q]) d = kCy[q] > 0 ? d + vy : d - vy;
+            if (kCz[q]) d = kCz[q] > 0 ? d + vz : d - vz;
+            return d;
+          };
+          const R cu = cdot(ux, uy, uz), cg = cdot(gxr, gyr, gzr);
+          const D E = (D)wq(q) * omd, O = ((D)wq(q) * om3) * cdot(Jx, Jy, Jz);
+          const R Ne = (R)wq(q) * fma(cu, fma(k45, cu, k9 * cg), C0), No = ((R)wq(q) * k3) * cg;
+          rs ^= rs << 13;
+          rs ^= rs >> 17;
+          rs ^= rs << 5;
+          store(q, fma(om1, (D)h[q], (E + O) + (D)(Ne + No)), rs);
+          store(q + 1, fma(om1, (D)h[q + 1], (E - O) + (D)(Ne - No)), rs >> 16);
         }
       }
+    }
+    // latch this wave's health bits (one atomic per wave, only when some cell is bad)
+    if (__any(bad != 0u)) {
+      for (int o = 32; o > 0; o >>= 1) bad |= (uint32_t)__shfl_xor((int)bad, o);
+      if ((tid & 63) == 0) atomicOr((unsigned*)S.health, bad);
     }
     if (ib) __syncthreads();  // the next brick clears the field
   }
@@ -645,8 +674,12 @@ static void phase_impl(const SimDev* sims, const Items& it, int phase, int mode,
       launch_forces(ST, sims, it, mode, s);
       break;
     case kPhaseLattice:
-      hipLaunchKernelGGL(k_lattice<ST>, dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s, sims, it,
-                         mode);
+      if (it.moving_walls)
+        hipLaunchKernelGGL((k_lattice<ST, true>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s,
+                           sims, it, mode);
+      else
+        hipLaunchKernelGGL((k_lattice<ST, false>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s,
+                           sims, it, mode);
       break;
     case kPhaseInterp:
       launch_interp(ST, sims, it, mode, s);

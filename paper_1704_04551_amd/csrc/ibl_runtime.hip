@@ -41,6 +41,13 @@ ibl_status fail(ibl_status st, const std::string& msg) {
 
 constexpr int kGraphSteps = 16;
 
+// Executable graphs of 2^k timesteps, k = 0 .. 4 (the last is kGraphSteps).
+struct GraphSet {
+  static constexpr int kSizes = 5;
+  hipGraphExec_t g[kSizes] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+};
+static_assert(1 << (GraphSet::kSizes - 1) == kGraphSteps, "graph sizes");
+
 // Brick shape of a lattice: bs[0] x (kBrickThreads / bs[0]) x brick_depth cells,
 // bs[0] the descriptor's brick_x, or by default the widest of 64, 32, 16 that
 // the x extent fills (long x rows keep the streaming accesses in whole cache
@@ -81,11 +88,13 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 struct Layout {
   size_t f0, f1, u, g, rho, X, F, U, rec, escr, bcount, blist, bb0, fmax, lctl, hcount, hlist;
   size_t mesh_tmpl, mesh_off, mesh_ks, mesh_kb, mesh_mem, fext;
+  size_t mesh_rigid, bstate, bconst, bft, xr, ndv, node_mesh, gcount, glist, fm;
   size_t t_nn, t_node0, t_edge0, t_ne, inc_ptr, inc, ev, el0, ec0, es0, txref;
   size_t t_nt, t_tri0, ttri, ta0, tav0;
   size_t step, remaining, health, red, red_out, simdev, items;
   size_t total;
-  int64_t ncell, nbrick, ncube, nred;
+  int64_t ncell, nbrick, ncube, nred, ngrid;
+  int32_t ngm[3];
 };
 
 ibl_status check_desc(const ibl_sim_desc* d) {
@@ -100,6 +109,7 @@ ibl_status check_desc(const ibl_sim_desc* d) {
   if (d->brick_x != 0 && d->brick_x != 16 && d->brick_x != 32 && d->brick_x != 64)
     return fail(IBL_ERR_ARG, "brick_x must be 0, 16, 32 or 64");
   if (d->skin != 0 && d->skin != 1) return fail(IBL_ERR_ARG, "skin must be 0 or 1");
+  if (d->morse != 0 && d->morse != 1) return fail(IBL_ERR_ARG, "morse must be 0 or 1");
   if (d->delta < 0 || d->delta > 1) return fail(IBL_ERR_ARG, "unknown delta kernel");
   if (d->init_profile < 0 || d->init_profile > 1) return fail(IBL_ERR_ARG, "unknown init profile");
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||
@@ -164,6 +174,20 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.mesh_kb = take((size_t)d->max_meshes * 8);
   L.mesh_mem = take((size_t)d->max_meshes * 4 * 8);
   L.fext = take(3 * maxn * 8);
+  L.mesh_rigid = take((size_t)d->max_meshes * 4);
+  L.bstate = take((size_t)d->max_meshes * kBodyState * 8);
+  L.bconst = take((size_t)d->max_meshes * kBodyConst * 8);
+  L.bft = take((size_t)d->max_meshes * 6 * 8);
+  L.xr = take(3 * maxn * 8);
+  L.ndv = take(maxn * 8);
+  L.node_mesh = take(maxn * 4);
+  // Morse neighbour grid: cells at least 2 lattice units wide
+  L.ngrid = 0;
+  for (int a = 0; a < 3; ++a) L.ngm[a] = d->morse ? (d->n[a] / 2 > 0 ? d->n[a] / 2 : 1) : 0;
+  if (d->morse) L.ngrid = (int64_t)L.ngm[0] * L.ngm[1] * L.ngm[2];
+  L.gcount = take(2 * (size_t)L.ngrid * 4);
+  L.glist = take(2 * (size_t)L.ngrid * kMorseCap * 4);
+  L.fm = take(3 * maxn * 8);
   L.t_nn = take((size_t)d->max_templates * 4);
   L.t_node0 = take((size_t)d->max_templates * 4);
   L.t_edge0 = take((size_t)d->max_templates * 4);
@@ -214,12 +238,15 @@ struct ibl_sim_s {
   // per template: internal node i holds the caller's node perm[i] (spatial
   // order of the reference shape, so neighbouring nodes share cache lines)
   std::vector<std::vector<int>> t_perm;
+  std::vector<std::vector<int>> t_tris;  // per template: triangles, internal node numbering
   // meshes
   int nmesh = 0, nnodes = 0;
   std::vector<int> mesh_tmpl, mesh_off;
   int membrane = 0;  // some mesh has WLC-POW, area or volume terms
-  // graphs (invalidated when the work lists change)
-  hipGraphExec_t g1 = nullptr, gN = nullptr;
+  int rigid = 0;     // some mesh is a rigid body
+  std::vector<char> mesh_is_rigid;
+  // graphs of 1, 2, 4, 8, 16 steps (invalidated when the work lists change)
+  GraphSet graphs;
 };
 
 struct ibl_batch_s {
@@ -229,16 +256,17 @@ struct ibl_batch_s {
   SimDev* dsims = nullptr;
   int32_t* doffs = nullptr;
   Items items;
-  hipGraphExec_t g1 = nullptr, gN = nullptr;
+  GraphSet graphs;
   hipEvent_t ev = nullptr;
 };
 
 namespace {
 
-void drop_graphs(hipGraphExec_t& g1, hipGraphExec_t& gN) {
-  if (g1) (void)hipGraphExecDestroy(g1);
-  if (gN) (void)hipGraphExecDestroy(gN);
-  g1 = gN = nullptr;
+void drop_graphs(GraphSet& G) {
+  for (auto& g : G.g) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
 }
 
 // Capture `steps` timesteps of the given launch set into an executable graph.
@@ -272,21 +300,25 @@ __global__ void k_set_many(StepArgs a) {
   if (i < a.n) *a.ptr[i] = a.val[i];
 }
 
-// Run `n` steps: remaining <- n on every simulation of the set, then
-// replay the N-step graph and the 1-step graph.
-ibl_status run_steps(int storage, const SimDev* sims, const Items& it, hipStream_t s,
-                     hipGraphExec_t& g1, hipGraphExec_t& gN, int64_t nmax) {
+// Run `n` steps (remaining <- n on every simulation of the set, set by the
+// caller): replay the 16-step graph n / 16 times, then one graph of each
+// power of two in the binary expansion of n % 16.
+ibl_status run_steps(int storage, const SimDev* sims, const Items& it, hipStream_t s, GraphSet& G,
+                     int64_t nmax) {
   if (nmax <= 0) return IBL_OK;
-  if (!g1) {
-    ibl_status st = capture(storage, sims, it, s, 1, &g1);
-    if (st) return st;
+  const int64_t full = nmax / kGraphSteps;
+  const int rem = (int)(nmax % kGraphSteps);
+  for (int k = GraphSet::kSizes - 1; k >= 0; --k) {
+    const int len = 1 << k;
+    const bool need = (len == kGraphSteps) ? full > 0 : (rem & len) != 0;
+    if (need && !G.g[k]) {
+      ibl_status st = capture(storage, sims, it, s, len, &G.g[k]);
+      if (st) return st;
+    }
   }
-  if (nmax >= kGraphSteps && !gN) {
-    ibl_status st = capture(storage, sims, it, s, kGraphSteps, &gN);
-    if (st) return st;
-  }
-  for (int64_t k = 0; k + kGraphSteps <= nmax; k += kGraphSteps) HIPCHK(hipGraphLaunch(gN, s));
-  for (int64_t k = 0; k < nmax % kGraphSteps; ++k) HIPCHK(hipGraphLaunch(g1, s));
+  for (int64_t k = 0; k < full; ++k) HIPCHK(hipGraphLaunch(G.g[GraphSet::kSizes - 1], s));
+  for (int k = GraphSet::kSizes - 2; k >= 0; --k)
+    if (rem & (1 << k)) HIPCHK(hipGraphLaunch(G.g[k], s));
   return IBL_OK;
 }
 
@@ -319,8 +351,13 @@ ibl_status upload_simdev(ibl_sim S) {
   it.big_templates = S->big_templates;
   it.forces_variant = forces_variant();
   it.membrane = S->membrane;
+  it.moving_walls = 0;
+  for (int q = 0; q < kQ; ++q)
+    for (int l = 0; l < 6; ++l) it.moving_walls |= S->hd.bbw[q][l] != 0.0;
+  it.rigid = S->rigid;
+  it.morse = S->hd.morse[0] != 0.0 ? 1 : 0;
   it.sub = 0;
-  drop_graphs(S->g1, S->gN);
+  drop_graphs(S->graphs);
   return IBL_OK;
 }
 
@@ -340,11 +377,34 @@ void fields_to_host(const std::vector<char>& raw, int64_t count, double* out) {
   for (int64_t i = 0; i < count; ++i) out[i] = (double)p[i];
 }
 
+// plain streaming copy (calibration): 16-byte elements, grid-stride
+__global__ __launch_bounds__(256) void k_hbm_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                  int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* ibl_last_error(void) { return g_err.c_str(); }
+
+ibl_status ibl_hbm_copy(const void* src, void* dst, size_t bytes, void* stream) {
+  if (!src || !dst || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)dst % 16)
+    return fail(IBL_ERR_ARG, "copy: null buffer, or a size or address not a multiple of 16");
+  const int64_t n = (int64_t)(bytes / 16);
+  if (n == 0) return IBL_OK;
+  // 8 workgroups of 256 threads per compute unit, a multiple of the 8 XCDs
+  int dev = 0, cus = 256;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t need = (n + 255) / 256;
+  const int grid = (int)(need < 8LL * cus ? need : 8LL * cus);
+  hipLaunchKernelGGL(k_hbm_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, n);
+  HIPCHK(hipGetLastError());
+  return IBL_OK;
+}
 
 ibl_status ibl_sim_bytes(const ibl_sim_desc* desc, size_t* out_bytes) {
   if (!out_bytes) return fail(IBL_ERR_ARG, "null output");
@@ -405,6 +465,13 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.nbrick = L.nbrick;
   d.delta = desc->delta;
   d.tau = desc->tau;
+  d.om = 1.0 / desc->tau;
+  d.pre = 1.0 - 0.5 / desc->tau;
+  d.om1 = 1.0 - d.om;
+  d.a0 = 3.0 * d.om;
+  d.a1 = 4.5 * d.om;
+  d.b0 = 3.0 * d.pre;
+  d.b1 = 9.0 * d.pre;
   d.maxn = desc->max_nodes;
   d.skin = desc->skin;
   d.f[0] = A + L.f0;
@@ -432,6 +499,18 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
   d.mesh_kb = (double*)(A + L.mesh_kb);
   d.mesh_mem = (double*)(A + L.mesh_mem);
   d.Fext = (double*)(A + L.fext);
+  d.mesh_rigid = (int32_t*)(A + L.mesh_rigid);
+  d.bstate = (double*)(A + L.bstate);
+  d.bconst = (double*)(A + L.bconst);
+  d.bft = (double*)(A + L.bft);
+  d.Xr = (double*)(A + L.xr);
+  d.ndv = (double*)(A + L.ndv);
+  d.node_mesh = (int32_t*)(A + L.node_mesh);
+  d.gcount = (int32_t*)(A + L.gcount);
+  d.glist = (int32_t*)(A + L.glist);
+  d.Fm = (double*)(A + L.fm);
+  d.ngrid = L.ngrid;
+  for (int a = 0; a < 3; ++a) d.ngm[a] = L.ngm[a];
   d.t_nt = (int32_t*)(A + L.t_nt);
   d.t_tri0 = (int32_t*)(A + L.t_tri0);
   d.ttri = (int32_t*)(A + L.ttri);
@@ -474,7 +553,7 @@ ibl_status ibl_sim_destroy(ibl_sim S) {
   if (!S) return IBL_OK;
   (void)hipSetDevice(S->device);  // teardown: nothing to report to
   (void)hipStreamSynchronize(S->stream);
-  drop_graphs(S->g1, S->gN);
+  drop_graphs(S->graphs);
   if (S->own_stream) (void)hipStreamDestroy(S->stream);
   delete S;
   return IBL_OK;
@@ -634,6 +713,7 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   if (e) return fail(IBL_ERR_DEVICE, std::string("template upload: ") + hipGetErrorString(e));
   S->t_nn.push_back(nn);
   S->t_perm.push_back(perm);
+  S->t_tris.push_back(ttri);
   S->t_node0.push_back(n0);
   S->t_edge0.push_back(e0);
   if (nn > kLdsNodes || ne > kLdsEdges) S->big_templates = 1;
@@ -647,7 +727,22 @@ ibl_status ibl_template_add(ibl_sim S, int32_t nn, int32_t nt, const int32_t* tr
   return IBL_OK;
 }
 
-ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, double kb, int32_t* out_mesh) {
+}  // extern "C"
+
+namespace {
+
+// Shared by ibl_mesh_add and ibl_body_add: checks, node upload (internal
+// order), mesh tables.  `body` (rigid bodies only): state and constants
+// records and the per-node body-frame offsets and weights, internal order.
+struct BodyInit {
+  double state[kBodyState];
+  double cons[kBodyConst];
+  std::vector<double> xr;  // [3][nn] SoA
+  std::vector<double> dv;  // [nn]
+};
+
+ibl_status add_mesh(ibl_sim S, int32_t tmpl, const double* x, double ks, double kb, const BodyInit* body,
+                    int32_t* out_mesh) {
   if (!S || !x || !out_mesh) return fail(IBL_ERR_ARG, "null argument");
   if (tmpl < 0 || tmpl >= S->ntmpl) return fail(IBL_ERR_ARG, "unknown template");
   if (!isfinite(ks) || !isfinite(kb)) return fail(IBL_ERR_ARG, "non-finite ks or kb");
@@ -675,18 +770,165 @@ ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, dou
     HIPCHK(hipMemsetAsync(d.U + a * ms + off, 0, 8 * (size_t)nn, S->stream));
     HIPCHK(hipMemsetAsync(d.F + a * ms + off, 0, 8 * (size_t)nn, S->stream));
   }
+  const int32_t rigid = body ? 1 : 0;
+  {
+    std::vector<int32_t> nm((size_t)nn, (int32_t)S->nmesh);
+    HIPCHK(hipMemcpyAsync(d.node_mesh + off, nm.data(), 4 * (size_t)nn, hipMemcpyHostToDevice, S->stream));
+  }
   HIPCHK(hipMemcpyAsync(d.mesh_tmpl + S->nmesh, &tmpl, 4, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_off + S->nmesh, &off, 4, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_ks + S->nmesh, &ks, 8, hipMemcpyHostToDevice, S->stream));
   HIPCHK(hipMemcpyAsync(d.mesh_kb + S->nmesh, &kb, 8, hipMemcpyHostToDevice, S->stream));
+  HIPCHK(hipMemcpyAsync(d.mesh_rigid + S->nmesh, &rigid, 4, hipMemcpyHostToDevice, S->stream));
   const double no_terms[4] = {0.0, 0.0, 0.0, 0.0};
   HIPCHK(hipMemcpyAsync(d.mesh_mem + 4 * (size_t)S->nmesh, no_terms, 32, hipMemcpyHostToDevice, S->stream));
+  if (body) {
+    HIPCHK(hipMemcpyAsync(d.bstate + kBodyState * (size_t)S->nmesh, body->state, sizeof(body->state),
+                          hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(d.bconst + kBodyConst * (size_t)S->nmesh, body->cons, sizeof(body->cons),
+                          hipMemcpyHostToDevice, S->stream));
+    for (int a = 0; a < 3; ++a)
+      HIPCHK(hipMemcpyAsync(d.Xr + a * ms + off, body->xr.data() + (size_t)a * nn, 8 * (size_t)nn,
+                            hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(d.ndv + off, body->dv.data(), 8 * (size_t)nn, hipMemcpyHostToDevice, S->stream));
+  }
   HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // new nodes: rebuild at the next step
   HIPCHK(hipStreamSynchronize(S->stream));
   S->mesh_tmpl.push_back(tmpl);
   S->mesh_off.push_back(off);
+  S->mesh_is_rigid.push_back((char)rigid);
+  S->rigid |= rigid;
   S->nnodes += nn;
   *out_mesh = S->nmesh++;
+  return upload_simdev(S);
+}
+
+// Mass properties of a uniform solid of density dens bounded by a closed,
+// outward triangulated surface (nodes p, triangles tris): the solid is a sum
+// of signed tetrahedra (o, a, b, c) over the triangles, o the first node.
+// Each contributes its volume a . (b x c) / 6, its first moment (volume times
+// its centroid) and its second moment about o, V_t / 20 (aa^T + bb^T + cc^T
+// + ss^T) with s = a + b + c (the covariance of a tetrahedron with a vertex at
+// the origin).  Returns false for a surface enclosing no positive volume.
+bool solid_mass(const std::vector<double>& p, const std::vector<int>& tris, double dens, double& M,
+                double cm[3], double I[9]) {
+  double V = 0.0, m1[3] = {0.0, 0.0, 0.0}, m2[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const double* o = p.data();
+  for (size_t t = 0; t + 2 < tris.size(); t += 3) {
+    double a[3], b[3], c[3];
+    for (int k = 0; k < 3; ++k) {
+      a[k] = p[3 * (size_t)tris[t] + k] - o[k];
+      b[k] = p[3 * (size_t)tris[t + 1] + k] - o[k];
+      c[k] = p[3 * (size_t)tris[t + 2] + k] - o[k];
+    }
+    const double vt = (a[0] * (b[1] * c[2] - b[2] * c[1]) + a[1] * (b[2] * c[0] - b[0] * c[2]) +
+                       a[2] * (b[0] * c[1] - b[1] * c[0])) / 6.0;
+    V += vt;
+    for (int i = 0; i < 3; ++i) {
+      const double si = a[i] + b[i] + c[i];
+      m1[i] += vt * si * 0.25;
+      for (int j = 0; j < 3; ++j)
+        m2[3 * i + j] += vt * 0.05 * (a[i] * a[j] + b[i] * b[j] + c[i] * c[j] + si * (a[j] + b[j] + c[j]));
+    }
+  }
+  if (!(V > 0.0)) return false;
+  double r[3];
+  for (int i = 0; i < 3; ++i) r[i] = m1[i] / V;
+  // second moment about the centre of mass, then I = dens (tr(C) Id - C)
+  double C[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) C[3 * i + j] = m2[3 * i + j] - V * r[i] * r[j];
+  const double tr = C[0] + C[4] + C[8];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) I[3 * i + j] = dens * ((i == j ? tr : 0.0) - C[3 * i + j]);
+  M = dens * V;
+  for (int i = 0; i < 3; ++i) cm[i] = o[i] + r[i];
+  return true;
+}
+
+bool invert3(const double A[9], double B[9]) {
+  const double c00 = A[4] * A[8] - A[5] * A[7], c01 = A[5] * A[6] - A[3] * A[8], c02 = A[3] * A[7] - A[4] * A[6];
+  const double det = A[0] * c00 + A[1] * c01 + A[2] * c02;
+  if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+  const double id = 1.0 / det;
+  B[0] = c00 * id; B[1] = (A[2] * A[7] - A[1] * A[8]) * id; B[2] = (A[1] * A[5] - A[2] * A[4]) * id;
+  B[3] = c01 * id; B[4] = (A[0] * A[8] - A[2] * A[6]) * id; B[5] = (A[2] * A[3] - A[0] * A[5]) * id;
+  B[6] = c02 * id; B[7] = (A[1] * A[6] - A[0] * A[7]) * id; B[8] = (A[0] * A[4] - A[1] * A[3]) * id;
+  return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+ibl_status ibl_mesh_add(ibl_sim S, int32_t tmpl, const double* x, double ks, double kb, int32_t* out_mesh) {
+  return add_mesh(S, tmpl, x, ks, kb, nullptr, out_mesh);
+}
+
+ibl_status ibl_body_add(ibl_sim S, int32_t tmpl, const double* x, double density, const double* v0,
+                        const double* w0, int32_t* out_mesh) {
+  if (!S || !x || !out_mesh) return fail(IBL_ERR_ARG, "null argument");
+  if (tmpl < 0 || tmpl >= S->ntmpl) return fail(IBL_ERR_ARG, "unknown template");
+  if (!(density > 0.0) || !isfinite(density)) return fail(IBL_ERR_ARG, "density must be positive and finite");
+  for (int a = 0; a < 3; ++a)
+    if ((v0 && !isfinite(v0[a])) || (w0 && !isfinite(w0[a]))) return fail(IBL_ERR_ARG, "non-finite velocity");
+  const int nn = S->t_nn[tmpl];
+  const std::vector<int>& perm = S->t_perm[tmpl];
+  // node positions in internal order
+  std::vector<double> p(3 * (size_t)nn);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < 3; ++a) {
+      p[3 * (size_t)i + a] = x[3 * (size_t)perm[i] + a];
+      if (!isfinite(p[3 * (size_t)i + a])) return fail(IBL_ERR_ARG, "non-finite node coordinate");
+    }
+  BodyInit B;
+  double M, cm[3], I[9];
+  if (!solid_mass(p, S->t_tris[tmpl], density, M, cm, I) || !invert3(I, B.cons + 1))
+    return fail(IBL_ERR_ARG, "the body's surface encloses no volume");
+  B.cons[0] = M;
+  B.xr.assign(3 * (size_t)nn, 0.0);
+  B.dv.assign((size_t)nn, 0.0);
+  for (int i = 0; i < nn; ++i)
+    for (int a = 0; a < 3; ++a) B.xr[(size_t)a * nn + i] = p[3 * (size_t)i + a] - cm[a];
+  const std::vector<int>& tr = S->t_tris[tmpl];
+  for (size_t t = 0; t + 2 < tr.size(); t += 3) {
+    double e1[3], e2[3];
+    for (int a = 0; a < 3; ++a) {
+      e1[a] = p[3 * (size_t)tr[t + 1] + a] - p[3 * (size_t)tr[t] + a];
+      e2[a] = p[3 * (size_t)tr[t + 2] + a] - p[3 * (size_t)tr[t] + a];
+    }
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    const double share = 0.5 * sqrt(cx * cx + cy * cy + cz * cz) / 3.0;  // x one lattice spacing
+    for (int k = 0; k < 3; ++k) B.dv[(size_t)tr[t + k]] += share;
+  }
+  // state: centre of mass, identity orientation (the body frame is the frame
+  // of the given positions), velocity, angular momentum L = I w0
+  memset(B.state, 0, sizeof(B.state));
+  for (int a = 0; a < 3; ++a) {
+    B.state[a] = cm[a];
+    B.state[7 + a] = v0 ? v0[a] : 0.0;
+  }
+  B.state[3] = 1.0;
+  for (int a = 0; a < 3; ++a)
+    B.state[10 + a] = w0 ? I[3 * a] * w0[0] + I[3 * a + 1] * w0[1] + I[3 * a + 2] * w0[2] : 0.0;
+  return add_mesh(S, tmpl, x, 0.0, 0.0, &B, out_mesh);
+}
+
+ibl_status ibl_sim_morse(ibl_sim S, double D0, double alpha, double r0, double rc) {
+  if (!S) return fail(IBL_ERR_ARG, "null simulation");
+  if (!isfinite(D0) || D0 < 0.0 || !isfinite(alpha) || !(alpha > 0.0) || !isfinite(r0) || !isfinite(rc) ||
+      !(rc > 0.0))
+    return fail(IBL_ERR_ARG, "Morse parameters: D0 >= 0, alpha > 0, rc > 0, all finite");
+  if (!S->desc.morse) return fail(IBL_ERR_UNSUPPORTED, "the simulation was created without the Morse grid");
+  if (rc > 2.0) return fail(IBL_ERR_UNSUPPORTED, "Morse cutoff beyond 2 lattice units (the grid's cell width)");
+  HIPCHK(hipSetDevice(S->device));
+  S->hd.morse[0] = D0;
+  S->hd.morse[1] = alpha;
+  S->hd.morse[2] = r0;
+  S->hd.morse[3] = rc;
+  HIPCHK(hipStreamSynchronize(S->stream));
+  HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // both grids empty
   return upload_simdev(S);
 }
 
@@ -697,8 +939,7 @@ ibl_status ibl_mesh_membrane(ibl_sim S, int32_t mesh, double kbt_p, double kg, d
   for (double v : k)
     if (!isfinite(v) || v < 0.0) return fail(IBL_ERR_ARG, "membrane constants must be finite and >= 0");
   const int tm = S->mesh_tmpl[mesh];
-  if (S->t_big[tm])
-    return fail(IBL_ERR_UNSUPPORTED, "area, volume and WLC-POW terms need a template within the LDS force kernel");
+  if (S->mesh_is_rigid[mesh]) return fail(IBL_ERR_ARG, "a rigid body has no membrane energy");
   if ((kl != 0.0 && !(S->t_rest[tm][0] > 0.0)) || (kg != 0.0 && !(S->t_rest[tm][1] > 0.0)) ||
       (kv != 0.0 && !(S->t_rest[tm][2] > 0.0)))
     return fail(IBL_ERR_ARG, "reference shape with a degenerate triangle or no enclosed volume");
@@ -715,7 +956,7 @@ ibl_status ibl_step(ibl_sim S, int64_t n) {
   HIPCHK(hipSetDevice(S->device));
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, S->stream, S->hd.remaining, n);
   HIPCHK(hipGetLastError());
-  return run_steps(S->desc.storage, S->dd, S->items, S->stream, S->g1, S->gN, n);
+  return run_steps(S->desc.storage, S->dd, S->items, S->stream, S->graphs, n);
 }
 
 ibl_status ibl_sync(ibl_sim S) {
@@ -793,6 +1034,36 @@ ibl_status ibl_read_nodes(ibl_sim S, int32_t mesh, double* x, double* u, double*
   return IBL_OK;
 }
 
+ibl_status ibl_read_body(ibl_sim S, int32_t mesh, double* out) {
+  if (!S || !out) return fail(IBL_ERR_ARG, "null argument");
+  if (mesh < 0 || mesh >= S->nmesh) return fail(IBL_ERR_ARG, "unknown mesh");
+  if (!S->mesh_is_rigid[mesh]) return fail(IBL_ERR_ARG, "not a rigid body");
+  ibl_status st = observe(S);  // force and torque at the current state
+  if (st) return st;
+  double bs[kBodyState], bc[kBodyConst], ft[6];
+  HIPCHK(hipMemcpy(bs, S->hd.bstate + kBodyState * (size_t)mesh, sizeof(bs), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(bc, S->hd.bconst + kBodyConst * (size_t)mesh, sizeof(bc), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(ft, S->hd.bft + 6 * (size_t)mesh, sizeof(ft), hipMemcpyDeviceToHost));
+  // Omega = R Ib^-1 R^T L
+  const double w = bs[3], x = bs[4], y = bs[5], z = bs[6];
+  const double R[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - z * w), 2 * (x * z + y * w),
+                       2 * (x * y + z * w), 1 - 2 * (x * x + z * z), 2 * (y * z - x * w),
+                       2 * (x * z - y * w), 2 * (y * z + x * w), 1 - 2 * (x * x + y * y)};
+  double t[3], t2[3], om[3];
+  for (int a = 0; a < 3; ++a) t[a] = R[a] * bs[10] + R[3 + a] * bs[11] + R[6 + a] * bs[12];
+  for (int a = 0; a < 3; ++a) t2[a] = bc[1 + 3 * a] * t[0] + bc[2 + 3 * a] * t[1] + bc[3 + 3 * a] * t[2];
+  for (int a = 0; a < 3; ++a) om[a] = R[3 * a] * t2[0] + R[3 * a + 1] * t2[1] + R[3 * a + 2] * t2[2];
+  for (int a = 0; a < 3; ++a) {
+    out[a] = bs[a];          // centre of mass
+    out[7 + a] = bs[7 + a];  // velocity
+    out[10 + a] = om[a];     // angular velocity
+    out[13 + a] = ft[a];     // force
+    out[16 + a] = ft[3 + a]; // torque
+  }
+  for (int a = 0; a < 4; ++a) out[3 + a] = bs[3 + a];  // orientation
+  return IBL_OK;
+}
+
 ibl_status ibl_conservation(ibl_sim S, double* mass, double momentum[3], uint32_t* health) {
   if (!S) return fail(IBL_ERR_ARG, "null simulation");
   HIPCHK(hipSetDevice(S->device));
@@ -828,7 +1099,7 @@ struct StateHeader {
 ibl_status ibl_state_bytes(ibl_sim S, size_t* out) {
   if (!S || !out) return fail(IBL_ERR_ARG, "null argument");
   *out = sizeof(StateHeader) + (size_t)kQ * S->L.ncell * storage_bytes(S->desc.storage) +
-         (size_t)3 * S->nnodes * 8;
+         (size_t)3 * S->nnodes * 8 + (size_t)S->nmesh * kBodyState * 8;
   return IBL_OK;
 }
 
@@ -842,7 +1113,7 @@ ibl_status ibl_read_state(ibl_sim S, void* buf, size_t bytes) {
   if (st) return st;
   StateHeader h;
   memset(&h, 0, sizeof(h));
-  memcpy(h.magic, "IBLSTAT1", 8);
+  memcpy(h.magic, "IBLSTAT2", 8);
   h.storage = S->desc.storage;
   for (int a = 0; a < 3; ++a) h.n[a] = S->desc.n[a];
   h.nnodes = S->nnodes;
@@ -857,6 +1128,8 @@ ibl_status ibl_read_state(ibl_sim S, void* buf, size_t bytes) {
     HIPCHK(hipMemcpy(p, S->hd.X + (size_t)a * S->desc.max_nodes, 8 * (size_t)S->nnodes, hipMemcpyDeviceToHost));
     p += 8 * (size_t)S->nnodes;
   }
+  if (S->nmesh)  // rigid-body states (unused records for capsules)
+    HIPCHK(hipMemcpy(p, S->hd.bstate, (size_t)S->nmesh * kBodyState * 8, hipMemcpyDeviceToHost));
   return IBL_OK;
 }
 
@@ -867,7 +1140,7 @@ ibl_status ibl_write_state(ibl_sim S, const void* buf, size_t bytes) {
   if (!buf || bytes < need) return fail(IBL_ERR_ARG, "state buffer too small");
   StateHeader h;
   memcpy(&h, buf, sizeof(h));
-  if (memcmp(h.magic, "IBLSTAT1", 8) != 0 || h.storage != S->desc.storage || h.nnodes != S->nnodes ||
+  if (memcmp(h.magic, "IBLSTAT2", 8) != 0 || h.storage != S->desc.storage || h.nnodes != S->nnodes ||
       h.n[0] != S->desc.n[0] || h.n[1] != S->desc.n[1] || h.n[2] != S->desc.n[2] || h.step < 0)
     return fail(IBL_ERR_ARG, "state does not match this simulation");
   HIPCHK(hipSetDevice(S->device));
@@ -880,6 +1153,7 @@ ibl_status ibl_write_state(ibl_sim S, const void* buf, size_t bytes) {
     HIPCHK(hipMemcpy(S->hd.X + (size_t)a * S->desc.max_nodes, p, 8 * (size_t)S->nnodes, hipMemcpyHostToDevice));
     p += 8 * (size_t)S->nnodes;
   }
+  if (S->nmesh) HIPCHK(hipMemcpy(S->hd.bstate, p, (size_t)S->nmesh * kBodyState * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(S->hd.step, &h.step, 8, hipMemcpyHostToDevice));
   HIPCHK(launch_reset_lists(S->dd, S->L.nbrick, S->stream));  // positions replaced: rebuild
   HIPCHK(hipStreamSynchronize(S->stream));
@@ -968,9 +1242,15 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.cube_off = B->doffs + 3 * (n + 1);
   it.big_templates = 0;
   it.membrane = 0;
+  it.moving_walls = 0;
+  it.rigid = 0;
+  it.morse = 0;
   for (int i = 0; i < n; ++i) {
     it.big_templates |= sims[i]->big_templates;
     it.membrane |= sims[i]->membrane;
+    it.moving_walls |= sims[i]->items.moving_walls;
+    it.rigid |= sims[i]->rigid;
+    it.morse |= sims[i]->items.morse;
   }
   it.forces_variant = forces_variant();
   it.sub = 0;
@@ -1003,7 +1283,7 @@ ibl_status ibl_batch_step(ibl_batch B, const int64_t* steps) {
     hipLaunchKernelGGL(k_set_many, dim3(1), dim3(64), 0, B->stream, a);
     HIPCHK(hipGetLastError());
   }
-  ibl_status st = run_steps(B->storage, B->dsims, B->items, B->stream, B->g1, B->gN, nmax);
+  ibl_status st = run_steps(B->storage, B->dsims, B->items, B->stream, B->graphs, nmax);
   if (st) return st;
   HIPCHK(hipEventRecord(B->ev, B->stream));
   for (int i = 1; i < n; ++i)
@@ -1015,7 +1295,7 @@ ibl_status ibl_batch_destroy(ibl_batch B) {
   if (!B) return IBL_OK;
   (void)hipSetDevice(B->sims[0]->device);  // teardown: nothing to report to
   (void)hipStreamSynchronize(B->stream);
-  drop_graphs(B->g1, B->gN);
+  drop_graphs(B->graphs);
   (void)hipFree(B->dsims);
   (void)hipFree(B->doffs);
   (void)hipEventDestroy(B->ev);

@@ -50,6 +50,7 @@ class SimDesc(ctypes.Structure):
         ("max_template_edges", ctypes.c_int32),
         ("brick_x", ctypes.c_int32),
         ("skin", ctypes.c_int32),
+        ("morse", ctypes.c_int32),
     ]
 
 
@@ -72,6 +73,10 @@ def lib():
             "ibl_template_add": [P, I32, I32, P, P, ctypes.POINTER(I32)],
             "ibl_mesh_add": [P, I32, P, D, D, ctypes.POINTER(I32)],
             "ibl_mesh_membrane": [P, I32, D, D, D, D],
+            "ibl_body_add": [P, I32, P, D, P, P, ctypes.POINTER(I32)],
+            "ibl_read_body": [P, I32, P],
+            "ibl_sim_morse": [P, D, D, D, D],
+            "ibl_hbm_copy": [P, P, ctypes.c_size_t, P],
             "ibl_step": [P, I64],
             "ibl_sync": [P],
             "ibl_read_fields": [P, P, P, P],
@@ -110,7 +115,7 @@ def _p(a):
 
 def make_desc(n, tau, g_body=(0, 0, 0), wall=(0, 0, 0), u_lo=None, u_hi=None, storage="f32",
               delta="cos", init_profile=0, max_nodes=0, max_meshes=0, max_templates=0,
-              max_template_nodes=0, max_template_edges=0, brick_x=0, skin=0) -> SimDesc:
+              max_template_nodes=0, max_template_edges=0, brick_x=0, skin=0, morse=0) -> SimDesc:
     d = SimDesc()
     for a in range(3):
         d.n[a] = int(n[a])
@@ -133,6 +138,7 @@ def make_desc(n, tau, g_body=(0, 0, 0), wall=(0, 0, 0), u_lo=None, u_hi=None, st
     d.max_template_edges = int(max_template_edges)
     d.brick_x = int(brick_x)
     d.skin = int(skin)
+    d.morse = int(morse)
     return d
 
 
@@ -183,6 +189,32 @@ class Sim:
         _check(lib().ibl_mesh_add(self.h, int(template), _p(x), float(ks), float(kb), ctypes.byref(out)))
         self._mesh_nn.append(x.shape[0])
         return out.value
+
+    def add_body(self, template, x, density=1.0, v0=(0.0, 0.0, 0.0), w0=(0.0, 0.0, 0.0)) -> int:
+        """A rigid body: the template's surface at x (shape and initial pose),
+        uniform density, initial velocity and angular velocity.  Returns its
+        mesh index."""
+        x = np.ascontiguousarray(x, np.float64)
+        if x.shape != (self._tmpl_nn[template], 3):
+            raise ValueError("node array does not match the template")
+        v = np.ascontiguousarray(v0, np.float64)
+        w = np.ascontiguousarray(w0, np.float64)
+        out = ctypes.c_int32()
+        _check(lib().ibl_body_add(self.h, int(template), _p(x), float(density), _p(v), _p(w), ctypes.byref(out)))
+        self._mesh_nn.append(x.shape[0])
+        return out.value
+
+    def body(self, mesh) -> dict:
+        """Rigid-body state at the current time: centre of mass xc, orientation
+        q (w, x, y, z), velocity v, angular velocity w, force and torque."""
+        o = np.zeros(19)
+        _check(lib().ibl_read_body(self.h, int(mesh), _p(o)))
+        return {"xc": o[0:3], "q": o[3:7], "v": o[7:10], "w": o[10:13], "force": o[13:16], "torque": o[16:19]}
+
+    def set_morse(self, D0, alpha, r0, rc):
+        """Morse repulsion between capsules, Eq. (13) (D0 = 0: off); the
+        simulation must have been created with morse=1."""
+        _check(lib().ibl_sim_morse(self.h, float(D0), float(alpha), float(r0), float(rc)))
 
     def set_membrane(self, mesh, kbtp=0.0, kg=0.0, kl=0.0, kv=0.0):
         """WLC-POW stretching (kbtp = kBT/p), global / local area (kg, kl) and
@@ -284,8 +316,11 @@ class Sim:
         desc = make_desc(spec.n, spec.tau, spec.g_body, spec.wall, spec.u_lo, spec.u_hi, storage,
                          spec.delta, spec.init_profile, max_nodes=nodes,
                          max_meshes=len(spec.capsules), max_templates=len(groups),
-                         max_template_nodes=tn, max_template_edges=te, brick_x=brick_x, skin=skin)
+                         max_template_nodes=tn, max_template_edges=te, brick_x=brick_x, skin=skin,
+                         morse=1 if spec.morse else 0)
         sim = cls(desc, device=device, arena=arena)
+        if spec.morse:
+            sim.set_morse(*spec.morse)
         mesh_of = {}
         for grp in groups:
             c0 = spec.capsules[grp[0]]
@@ -293,10 +328,26 @@ class Sim:
             for ci in grp:
                 mesh_of[ci] = t
         for ci, c in enumerate(spec.capsules):
+            if c.rigid:
+                sim.add_body(mesh_of[ci], c.x, c.density)
+                continue
             m = sim.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
             if any(c.membrane):
                 sim.set_membrane(m, *c.membrane)
         return sim
+
+
+def hbm_copy(src, dst, stream=None):
+    """Plain streaming copy of the device tensor src into dst (same byte
+    size, a multiple of 16): the memory-system calibration kernel, launched on
+    `stream` (a torch stream; default: torch's current one)."""
+    import torch
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nb:
+        raise ValueError("copy: sizes differ")
+    st = stream if stream is not None else torch.cuda.current_stream(src.device)
+    _check(lib().ibl_hbm_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
+                              ctypes.c_void_p(st.cuda_stream)))
 
 
 class Batch:

@@ -131,6 +131,8 @@ class Capsule:
     kb: float
     shape_key: str = ""    # capsules with equal keys share one reference state
     membrane: tuple = (0.0, 0.0, 0.0, 0.0)  # kBT/p (WLC-POW), kg, kl (area), kv (volume)
+    rigid: bool = False    # a rigid body (the surface at x moves as one body; ks, kb unused)
+    density: float = 1.0   # of a rigid body (the fluid's is 1)
 
 
 @dataclass
@@ -147,6 +149,7 @@ class SimSpec:
     steps: int = 1
     seed: int = 0
     name: str = ""
+    morse: tuple = ()      # (D0, alpha, r0, rc) of the inter-capsule repulsion, or () for none
 
     @property
     def cells(self) -> int:
@@ -301,7 +304,10 @@ def config_poiseuille(n=(64, 64, 256), tau=0.8, g=1e-6, axis=2, wall_axis=0, ste
 
 def config_batched(count=64, seed=1004, steps=500, edges=(32, 48, 64, 96)):
     """Uneven batch: per sim, each edge uniform from `edges`; plates on z
-    moving +-U with shear rate uniform in [0.001, 0.01]; tau uniform in
+    moving at +-U with U uniform in [0.001, 0.01] lattice units per step (the
+    configuration's "wall shear rates" carry the unit of a velocity, and read
+    as shear rates they would move the 96-cell channels' walls past the
+    low-Mach bound of 0.3); tau uniform in
     [0.6, 1.2]; 1-8 sphere/ellipsoid capsules (642 nodes, aspect ratio 1-4,
     equal-volume radius 4) placed with 2 lu clearance."""
     sims = []
@@ -309,8 +315,7 @@ def config_batched(count=64, seed=1004, steps=500, edges=(32, 48, 64, 96)):
     for i in range(count):
         rng = np.random.default_rng(seed + 7919 * i)
         n = tuple(int(rng.choice(edges)) for _ in range(3))
-        gamma = rng.uniform(0.001, 0.01)
-        U = gamma * (n[2] - 2) / 2.0
+        U = rng.uniform(0.001, 0.01)
         u_lo, u_hi = _couette_walls(2, U, -U)
         tau = rng.uniform(0.6, 1.2)
         ncap = int(rng.integers(1, 9))

@@ -9,17 +9,32 @@ from paper_1704_04551_amd.workloads import template_groups
 def oracle_from_spec(spec):
     s = oracle.OracleSim(spec.n, spec.tau, g_body=spec.g_body, wall=spec.wall, u_lo=spec.u_lo,
                          u_hi=spec.u_hi, delta=spec.delta, init_profile=spec.init_profile)
+    if spec.morse:
+        s.set_morse(*spec.morse)
     mesh_of = {}
     for grp in template_groups(spec):
         c0 = spec.capsules[grp[0]]
         t = s.add_template(c0.tris, c0.x_ref)
         for ci in grp:
             mesh_of[ci] = t
+    # the library counts rigid bodies as meshes; the oracle keeps them apart:
+    # s.objects[i] = ("mesh", oracle mesh index) or ("body", oracle body index)
+    s.objects = []
     for ci, c in enumerate(spec.capsules):
+        if c.rigid:
+            s.objects.append(("body", s.add_body(mesh_of[ci], c.x, c.density)))
+            continue
         m = s.add_mesh(mesh_of[ci], c.x, c.ks, c.kb)
+        s.objects.append(("mesh", m))
         if any(c.membrane):
             s.set_membrane(m, *c.membrane)
     return s
+
+
+def oracle_nodes(o, i):
+    """(X, U, F) of object i of a spec in the oracle built by oracle_from_spec."""
+    kind, k = o.objects[i]
+    return o.body_nodes(k) if kind == "body" else o.nodes(k)
 
 
 def fluid_mask(spec):

@@ -213,3 +213,49 @@ def test_membrane_terms_with_alternative_force_kernels(variant, monkeypatch):
     finally:
         g.close()
         o.close()
+
+
+def _big_spec(terms=TERMS):
+    """The paper's finer membrane resolution (Sec. 3.2): an icosphere(4)
+    capsule of 2562 nodes (radius 7), squeezed and stretched as in _spec, in
+    plane Couette flow."""
+    S, T = W.icosphere(4)
+    n = (36, 28, 28)
+    cen = (np.array(n) - 1) / 2.0
+    xr = S * 7.0 + cen
+    x = cen + (xr - cen) * 0.97 * np.array([1.04, 1.0, 0.98])
+    ulo = np.zeros((3, 3)); uhi = np.zeros((3, 3))
+    ulo[2, 0] = -0.005; uhi[2, 0] = 0.005
+    cap = W.Capsule(x, xr, T, 0.0, 2e-3, "ico4", membrane=tuple(terms))
+    return W.SimSpec(n=n, tau=0.9, wall=(0, 0, 1), u_lo=ulo, u_hi=uhi, delta="cos", init_profile=1,
+                     capsules=[cap], name="membrane-2562")
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_membrane_terms_2562_node_template(storage):
+    """Templates above the LDS kernels' 642 nodes (their sums kept in HBM):
+    forces at the initial positions, then 100 coupled steps, against the
+    oracle."""
+    spec = _big_spec()
+    assert spec.capsules[0].x.shape[0] == 2562
+    g = ibl.Sim.from_spec(spec, storage=storage)
+    o = oracle_from_spec(spec)
+    try:
+        _, _, Fg = g.nodes(0)
+        _, _, Fo = o.nodes(0)
+        assert np.abs(Fo).max() > 1e-4
+        assert np.abs(Fg - Fo).max() < F_ABS[storage], np.abs(Fg - Fo).max()
+        g.step(100)
+        g.sync()
+        o.step(100)
+        _, ug, _ = g.fields(rho=False, g=False)
+        _, uo, _ = o.observe()
+        eu = field_err(ug, uo, fluid_mask(spec))
+        assert eu[0] < TOL[storage], eu
+        Xg = g.nodes(0)[0]
+        Xo = o.nodes(0)[0]
+        dx, rel = node_err(Xg, Xo, spec.capsules[0].x)
+        assert rel < TOL[storage] or dx < 1e-12, (dx, rel)
+    finally:
+        g.close()
+        o.close()

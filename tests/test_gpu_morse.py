@@ -1,0 +1,125 @@
+"""Inter-capsule Morse repulsion on the GPU (Eq. (13), Sec. 2.2) against the
+FP64 oracle, and its determinism (alone, in a batch, across a checkpoint).
+
+The library bins capsule nodes into a neighbour grid of 2-lattice-unit cells
+and sums each node's pair forces exactly (two-word fixed point); the oracle
+visits every pair of nodes of different capsules.  Bars as for the capsules:
+FP64 storage about 1e-11 relative, FP32 1e-5."""
+import numpy as np
+import pytest
+
+from paper_1704_04551_amd import ibl
+from paper_1704_04551_amd import workloads as W
+
+from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-11, "f32": 1e-5}
+MORSE = (2.4e-3, 1.0, 1.2, 1.2)  # D0, alpha, r0, rc (rc = r0: repulsion only)
+
+
+def _ring_spec(n=(20, 16, 16), morse=MORSE, U=0.004):
+    """Three spherical capsules (radius 3) in a ring around the periodic x
+    axis, node gaps 0.4, 0.6 and 1.0 lu (the last across the periodic
+    boundary), in a gentle shear between walls on z."""
+    S, T = W.icosphere(2)
+    caps = []
+    for xc in (6.6, 13.0, 19.6):
+        x = S * 3.0 + np.array([xc, 7.7, 7.6])
+        caps.append(W.Capsule(x, x.copy(), T, 0.02, 0.004, "sphere3"))
+    ulo = np.zeros((3, 3)); uhi = np.zeros((3, 3))
+    ulo[2, 0] = -U; uhi[2, 0] = U
+    return W.SimSpec(n=n, tau=0.9, wall=(0, 0, 1), u_lo=ulo, u_hi=uhi, delta="cos", init_profile=1,
+                     capsules=caps, name="morse-ring", morse=morse)
+
+
+def test_morse_forces_at_step0_f64():
+    """Node forces at time 0 (membrane at rest, so only Eq. (13) acts): the
+    GPU's equal the oracle's pair sums to round-off, and they are not zero."""
+    spec = _ring_spec()
+    g = ibl.Sim.from_spec(spec, storage="f64")
+    o = oracle_from_spec(spec)
+    o.observe()
+    fmax = 0.0
+    for i in range(len(spec.capsules)):
+        Fg = g.nodes(i)[2]
+        Fo = o.nodes(i)[2]
+        fmax = max(fmax, np.abs(Fo).max())
+        assert np.abs(Fg - Fo).max() < 1e-13 * np.abs(Fo).max(), i
+    assert fmax > 1e-4
+    # the total is zero: pair forces are exact opposites (across the boundary too)
+    tot = sum(g.nodes(i)[2].sum(0) for i in range(len(spec.capsules)))
+    assert np.abs(tot).max() < 1e-15
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_morse_ring_vs_oracle(storage):
+    """200 coupled steps: fluid velocity and node positions against the
+    oracle, at the storage's bar."""
+    spec = _ring_spec()
+    g = ibl.Sim.from_spec(spec, storage=storage)
+    o = oracle_from_spec(spec)
+    g.step(200)
+    g.sync()
+    o.step(200)
+    _, ug, _ = g.fields(rho=False, g=False)
+    _, uo, _ = o.observe()
+    eu = field_err(ug, uo, fluid_mask(spec))[0]
+    assert eu < TOL[storage], ("u", eu)
+    for i, c in enumerate(spec.capsules):
+        dx, rel = node_err(g.nodes(i)[0], o.nodes(i)[0], c.x)
+        assert rel < TOL[storage] or dx < 1e-12, ("X", i, dx, rel)
+
+
+def test_morse_pushes_capsules_apart():
+    """With the repulsion on, the two closest capsules separate faster than
+    without it (FP32, 200 steps)."""
+    sep = {}
+    for on in (False, True):
+        spec = _ring_spec(morse=MORSE if on else ())
+        g = ibl.Sim.from_spec(spec, storage="f32")
+        g.step(200)
+        g.sync()
+        sep[on] = np.linalg.norm(g.nodes(1)[0].mean(0) - g.nodes(0)[0].mean(0))
+        g.close()
+    assert sep[True] > sep[False] + 1e-4, sep
+
+
+@pytest.mark.parametrize("skin", [0, 1])
+def test_morse_batch_and_checkpoint_bitwise(skin):
+    """A simulation with the repulsion runs bitwise the same alone, in a
+    batch beside a simulation without it (uneven step counts), and across a
+    checkpoint round trip."""
+    spec = _ring_spec()
+    ref = ibl.Sim.from_spec(spec, storage="f32")
+    ref.step(80)
+    ref.sync()
+    a = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
+    b = ibl.Sim.from_spec(W.config_small(delta="cos", n=24), storage="f32")
+    B = ibl.Batch([a, b])
+    B.step([50, 70])
+    B.close()
+    blob = a.read_state()
+    c = ibl.Sim.from_spec(spec, storage="f32", skin=skin)
+    c.write_state(blob)
+    c.step(30)
+    c.sync()
+    assert np.array_equal(ref.fields()[1], c.fields()[1])
+    for i in range(len(spec.capsules)):
+        for k in range(3):
+            assert np.array_equal(ref.nodes(i)[k], c.nodes(i)[k]), (i, k)
+
+
+def test_morse_setter_rejects_bad_arguments():
+    d = ibl.make_desc((16, 16, 16), 0.9, wall=(0, 0, 1))
+    s = ibl.Sim(d)  # created without the grid
+    with pytest.raises(ibl.IBLError):
+        s.set_morse(*MORSE)
+    d = ibl.make_desc((16, 16, 16), 0.9, wall=(0, 0, 1), morse=1)
+    s = ibl.Sim(d)
+    for bad in ((1e-3, 1.0, 1.2, 2.5), (1e-3, 0.0, 1.2, 1.2), (-1.0, 1.0, 1.2, 1.2), (np.nan, 1.0, 1.2, 1.2)):
+        with pytest.raises(ibl.IBLError):
+            s.set_morse(*bad)
+    s.set_morse(*MORSE)
+    s.set_morse(0.0, 1.0, 1.2, 1.2)  # off again
