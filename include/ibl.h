@@ -295,6 +295,25 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n_sims, ibl_batch* out)
 ibl_status ibl_batch_step(ibl_batch batch, const int64_t* steps_per_sim);
 ibl_status ibl_batch_destroy(ibl_batch batch);
 
+/* The batch advance of ibl_batch_create + ibl_batch_step + ibl_batch_destroy in
+ * one call that allocates nothing, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid it).  Simulation i advances steps_per_sim[i] >= 0 steps, with results
+ * bitwise those of ibl_batch_step (and of each simulation alone).
+ *   - The batch's device tables (the members' descriptors, the work-item
+ *     prefix tables) live in a static device array of the library, sized for
+ *     at most 64 simulations (about 110 KB, held on each GPU the library runs
+ *     on until the process ends).  Every call on a GPU reuses that GPU's
+ *     array: calls that overlap on one GPU (on different streams) race.
+ *   - Kernels are launched directly on the first simulation's stream (no
+ *     graph: instantiating one allocates).  Work pending on the other
+ *     members' streams must be complete before the call; the call does not
+ *     order those streams.
+ *   - Asynchronous: ibl_sync on the first simulation waits for it.
+ * Errors: IBL_ERR_ARG (null or repeated simulation, mixed storage or device,
+ * n_sims outside 1 .. 64, a negative step count), IBL_ERR_DEVICE. */
+ibl_status ibl_batch_step_static(const ibl_sim* sims, int32_t n_sims, const int64_t* steps_per_sim);
+
 /* Calibration of the memory system, outside the method: a plain streaming
  * copy of `bytes` bytes from device buffer src to device buffer dst (16-byte
  * vector loads and stores, every workgroup striding over the whole range), on

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -376,6 +377,59 @@ void fields_to_host(const std::vector<char>& raw, int64_t count, double* out) {
   const R* p = (const R*)raw.data();
   for (int64_t i = 0; i < count; ++i) out[i] = (double)p[i];
 }
+
+}  // namespace
+
+// ------------------------------------------------ allocation-free batch --
+// ibl_batch_step_static keeps the batch's device tables -- the member
+// simulations' descriptors and the work-item prefix tables -- in this
+// file-scope device array instead of memory it allocates.  Each GPU holds its
+// own copy until the process ends.  In host code the array's name is not a
+// device address: the address comes from hipGetSymbolAddress, once per
+// device (static_tables), and only that address is passed to kernels.
+constexpr int kStaticBatchMax = 64;
+struct StaticBatchTables {
+  SimDev sims[kStaticBatchMax];
+  int32_t offs[4 * (kStaticBatchMax + 1)];  // lattice, reduction, mesh, cube prefixes
+};
+static __device__ __align__(256) StaticBatchTables scratch;
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+StaticBatchTables* g_static_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device `dev`.
+ibl_status static_tables(int dev, StaticBatchTables** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(IBL_ERR_UNSUPPORTED, "device index beyond the static table");
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    g_static_ptr[dev] = (StaticBatchTables*)p;
+  }
+  *out = g_static_ptr[dev];
+  return IBL_OK;
+}
+
+struct StaticBatchArgs {
+  const SimDev* src[kStaticBatchMax];
+  int32_t offs[4 * (kStaticBatchMax + 1)];
+  int32_t n;
+};
+
+// One block per simulation copies its device descriptor into the table;
+// block 0 also writes the prefix tables.
+__global__ void k_static_tables(StaticBatchArgs a, StaticBatchTables* t) {
+  const int i = blockIdx.x;
+  const uint32_t* src = (const uint32_t*)a.src[i];
+  uint32_t* dst = (uint32_t*)&t->sims[i];
+  for (int w = threadIdx.x; w < (int)(sizeof(SimDev) / 4); w += blockDim.x) dst[w] = src[w];
+  if (i == 0)
+    for (int w = threadIdx.x; w < 4 * (a.n + 1); w += blockDim.x) t->offs[w] = a.offs[w];
+}
+static_assert(sizeof(SimDev) % 4 == 0, "descriptor copied as 32-bit words");
 
 // plain streaming copy (calibration): 16-byte elements, grid-stride
 __global__ __launch_bounds__(256) void k_hbm_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
@@ -1300,6 +1354,78 @@ ibl_status ibl_batch_destroy(ibl_batch B) {
   (void)hipFree(B->doffs);
   (void)hipEventDestroy(B->ev);
   delete B;
+  return IBL_OK;
+}
+
+ibl_status ibl_batch_step_static(const ibl_sim* sims, int32_t n, const int64_t* steps) {
+  if (!sims || !steps) return fail(IBL_ERR_ARG, "null argument");
+  if (n <= 0) return fail(IBL_ERR_ARG, "at least one simulation");
+  if (n > kStaticBatchMax) return fail(IBL_ERR_ARG, "more simulations than the static table holds (64)");
+  int64_t nmax = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!sims[i]) return fail(IBL_ERR_ARG, "null simulation in batch");
+    if (sims[i]->desc.storage != sims[0]->desc.storage) return fail(IBL_ERR_ARG, "mixed storage in batch");
+    if (sims[i]->device != sims[0]->device) return fail(IBL_ERR_ARG, "mixed devices in batch");
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(IBL_ERR_ARG, "simulation listed twice");
+    if (steps[i] < 0) return fail(IBL_ERR_ARG, "negative step count");
+    nmax = steps[i] > nmax ? steps[i] : nmax;
+  }
+  HIPCHK(hipSetDevice(sims[0]->device));
+  StaticBatchTables* t = nullptr;
+  ibl_status st = static_tables(sims[0]->device, &t);
+  if (st) return st;
+  hipStream_t s = sims[0]->stream;
+  StaticBatchArgs a;
+  a.n = n;
+  int32_t* lat = a.offs;
+  int32_t* red = lat + (n + 1);
+  int32_t* msh = red + (n + 1);
+  int32_t* cub = msh + (n + 1);
+  lat[0] = red[0] = msh[0] = cub[0] = 0;
+  Items it;
+  memset(&it, 0, sizeof(it));
+  for (int i = 0; i < n; ++i) {
+    const Items& si = sims[i]->items;
+    a.src[i] = sims[i]->dd;
+    lat[i + 1] = lat[i] + si.lat_total;
+    red[i + 1] = red[i] + si.red_total;
+    msh[i + 1] = msh[i] + si.mesh_total;
+    cub[i + 1] = cub[i] + si.cube_total;
+    it.big_templates |= sims[i]->big_templates;
+    it.membrane |= sims[i]->membrane;
+    it.moving_walls |= si.moving_walls;
+    it.rigid |= sims[i]->rigid;
+    it.morse |= si.morse;
+  }
+  it.nsim = n;
+  it.lat_total = lat[n];
+  it.red_total = red[n];
+  it.mesh_total = msh[n];
+  it.cube_total = cub[n];
+  it.lat_off = t->offs;  // device addresses inside the table (no dereference here)
+  it.red_off = t->offs + (n + 1);
+  it.mesh_off = t->offs + 2 * (n + 1);
+  it.cube_off = t->offs + 3 * (n + 1);
+  it.forces_variant = forces_variant();
+  it.sub = 0;
+  hipLaunchKernelGGL(k_static_tables, dim3(n), dim3(256), 0, s, a, t);
+  HIPCHK(hipGetLastError());
+  StepArgs sa;
+  sa.n = n;
+  for (int i = 0; i < n; ++i) {
+    sa.ptr[i] = sims[i]->hd.remaining;
+    sa.val[i] = steps[i];
+  }
+  hipLaunchKernelGGL(k_set_many, dim3(1), dim3(64), 0, s, sa);
+  HIPCHK(hipGetLastError());
+  // plain launches (instantiating a graph would allocate): sequences of
+  // kGraphSteps steps, then the rest
+  const SimDev* ds = t->sims;
+  for (int64_t k = 0; k < nmax; k += kGraphSteps) {
+    const int len = (int)(nmax - k < kGraphSteps ? nmax - k : kGraphSteps);
+    HIPCHK(launch_steps(sims[0]->desc.storage, ds, it, len, 0, s));
+  }
   return IBL_OK;
 }
 

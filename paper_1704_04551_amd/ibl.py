@@ -90,6 +90,7 @@ def lib():
             "ibl_batch_create": [P, I32, ctypes.POINTER(P)],
             "ibl_batch_step": [P, P],
             "ibl_batch_destroy": [P],
+            "ibl_batch_step_static": [P, I32, P],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -348,6 +349,18 @@ def hbm_copy(src, dst, stream=None):
     st = stream if stream is not None else torch.cuda.current_stream(src.device)
     _check(lib().ibl_hbm_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), nb,
                               ctypes.c_void_p(st.cuda_stream)))
+
+
+def batch_step_static(sims, steps):
+    """Advance simulation i by steps[i] through the allocation-free batch entry
+    point (device tables in the library's static array, plain launches on the
+    first simulation's stream)."""
+    sims = list(sims)
+    st = np.ascontiguousarray(steps, np.int64)
+    if st.shape != (len(sims),):
+        raise ValueError("one step count per simulation")
+    arr = (ctypes.c_void_p * len(sims))(*[s.h.value for s in sims])
+    _check(lib().ibl_batch_step_static(arr, len(sims), _p(st)))
 
 
 class Batch:
