@@ -202,15 +202,21 @@ __global__ void k_template_rest(const SimDev* __restrict__ sim, int tmpl, int ne
 // (31 - 27, 63 - 58, 20 - 16) times max|F| per cell, while the delta kernel's
 // partition of unity bounds a cell's sum by max|F| times the nodes per cell.
 //
-// FP32: the x and y sums share one 64-bit word, y 2^32 + x, so one 64-bit
-// atomic adds both (z takes a 32-bit one).  The word's sum is exactly
-// (sum y) 2^32 + (sum x); the low 32 bits, sign-extended, give sum x as long
-// as it fits in 32 bits (the headroom above), and the rest gives sum y.
+// Shares are rounded to the nearest integer, halves up (floor(v + 1/2), one
+// instruction): the rounding is the same wherever a share is formed.
+//
+// FP32: three 32-bit sums per cell, one LDS atomic each at a common address
+// (x, y and z planes of the field).
 //
 // FP16 storage: all three sums share one 64-bit word in 21-bit fields,
 // z 2^42 + y 2^21 + x, with kBits = 16 (8 B per cell, for bricks twice as
 // deep).  The resolution, 2^-16 of the step's largest force, is far below
 // the binary16 rounding of the populations that the force feeds.
+__device__ __forceinline__ int round_half_up(float v) {
+  int r;
+  asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(r) : "v"(v));
+  return r;
+}
 template <typename R>
 struct FixAcc;
 template <>
@@ -218,24 +224,18 @@ struct FixAcc<float> {
   static constexpr int kBits = 27;
   static constexpr int kCells = kBrickThreads * brick_depth(kF32);
   struct Field {
-    long long xy[kCells];
-    int32_t z[kCells];
+    int32_t c[3][kCells];
   };
-  __device__ static void clear(Field& f, int li) {
-    f.xy[li] = 0;
-    f.z[li] = 0;
-  }
+  __device__ static void clear(Field& f, int li) { f.c[0][li] = f.c[1][li] = f.c[2][li] = 0; }
   __device__ static void add(Field& f, int li, float gx, float gy, float gz) {
-    const long long w = (long long)__float2int_rn(gy) * 4294967296LL + (long long)__float2int_rn(gx);
-    atomicAdd((unsigned long long*)&f.xy[li], (unsigned long long)w);
-    atomicAdd(&f.z[li], __float2int_rn(gz));
+    atomicAdd(&f.c[0][li], round_half_up(gx));
+    atomicAdd(&f.c[1][li], round_half_up(gy));
+    atomicAdd(&f.c[2][li], round_half_up(gz));
   }
   __device__ static void get(const Field& f, int li, float inv, float& gx, float& gy, float& gz) {
-    const long long w = f.xy[li];
-    const long long lo = (long long)(int32_t)(uint32_t)w;
-    gx = (float)lo * inv;
-    gy = (float)((w - lo) >> 32) * inv;
-    gz = (float)f.z[li] * inv;
+    gx = (float)f.c[0][li] * inv;
+    gy = (float)f.c[1][li] * inv;
+    gz = (float)f.c[2][li] * inv;
   }
 };
 struct FixAcc3 {
@@ -247,8 +247,8 @@ struct FixAcc3 {
   };
   __device__ static void clear(Field& f, int li) { f.xyz[li] = 0; }
   __device__ static void add(Field& f, int li, float gx, float gy, float gz) {
-    const long long w = (long long)__float2int_rn(gz) * (kF * kF) + (long long)__float2int_rn(gy) * kF +
-                        (long long)__float2int_rn(gx);
+    const long long w = (long long)round_half_up(gz) * (kF * kF) + (long long)round_half_up(gy) * kF +
+                        (long long)round_half_up(gx);
     atomicAdd((unsigned long long*)&f.xyz[li], (unsigned long long)w);
   }
   // low 21 bits as a signed field
