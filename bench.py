@@ -437,10 +437,19 @@ def main():
         ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
         assert bool(torch.equal(src, dst))
         ms_mean = sum(ms) / reps
+        # torch's own device copy, for comparison
+        dst.zero_()
+        ev[0].record()
+        for i in range(reps):
+            dst.copy_(src)
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        tms = [ev[i].elapsed_time(ev[i + 1]) for i in range(reps)]
         print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n, "launches": reps + 3,
                           "ms_mean": round(ms_mean, 5), "ms_min": round(min(ms), 5),
                           "gbps_mean": round(8 * n / ms_mean / 1e6, 1),
-                          "gbps_best": round(8 * n / min(ms) / 1e6, 1)}))
+                          "gbps_best": round(8 * n / min(ms) / 1e6, 1),
+                          "torch_copy_gbps_mean": round(8 * n * reps / sum(tms) / 1e6, 1)}))
         return
     if args.precision_sweep:
         precision_sweep(args)

@@ -67,6 +67,10 @@ struct Store<kF64> {
   __device__ static void put(GLB T* p, int64_t i, int, R hq) { p[i] = hq; }
   __device__ static void put_sr(GLB T* p, double v, uint32_t) { __builtin_nontemporal_store(v, p); }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return p[i]; }
+  // the stored value's own units (the same as h's here)
+  static constexpr double kScale = 1.0;
+  __device__ static R h_raw(const GLB T* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void put_raw_sr(GLB T* p, double v, uint32_t r16) { put_sr(p, v, r16); }
 };
 template <>
 struct Store<kF32> {
@@ -80,6 +84,9 @@ struct Store<kF32> {
     __builtin_nontemporal_store((float)sr_truncate<29>(v, r16), p);
   }
   __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)p[i]; }
+  static constexpr double kScale = 1.0;
+  __device__ static R h_raw(const GLB T* p) { return __builtin_nontemporal_load(p); }
+  __device__ static void put_raw_sr(GLB T* p, double v, uint32_t r16) { put_sr(p, v, r16); }
 };
 // binary16 holds 2^16 h_i: a power-of-two scale (exact) that moves the
 // binary16 normal range, [2^-14, 65504], to offsets in [2^-30, 0.9995]
@@ -103,12 +110,20 @@ struct Store<kF16> {
   // binary16 keeps 10 of binary32's 23 fraction bits: 13 random bits are added
   // below the last kept bit and the 13 bits cleared (on the FP32 bit pattern,
   // as sr_truncate does on FP64)
-  __device__ static void put_sr(GLB T* p, float v, uint32_t r16) {
-    const uint32_t b = __float_as_uint(v * (float)kF16Scale);
+  __device__ static void put_sr(GLB T* p, float v, uint32_t r16) { put_raw_sr(p, v * (float)kF16Scale, r16); }
+  __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
+  // in the stored units, 2^16 h (the collide-stream kernel works in them:
+  // scaling by a power of two commutes with every rounding, so its results
+  // are those of scaling each load and store)
+  static constexpr double kScale = kF16Scale;
+  __device__ static R h_raw(const GLB T* p) {
+    return __half2float(__ushort_as_half(__builtin_nontemporal_load((const GLB unsigned short*)p)));
+  }
+  __device__ static void put_raw_sr(GLB T* p, float v, uint32_t r16) {
+    const uint32_t b = __float_as_uint(v);
     const float o = __uint_as_float((b + (r16 & 0x1fffu)) & ~0x1fffu);
     __builtin_nontemporal_store(__half_as_ushort(__float2half_rn(o)), (GLB unsigned short*)p);
   }
-  __device__ static double hd(const GLB T* p, int64_t i, int) { return (double)h(p, i, 0); }
 };
 
 template <int ST>
@@ -369,7 +384,8 @@ __device__ __forceinline__ int pull_source(const SimDev& S, int q, int x, int y,
 
 // The 19 pulled populations of fluid cell (x, y, z) in the storage's compute
 // type (bounce-back links include their wall term, see above).
-template <int ST>
+// kRaw: the values in their stored units (Store<ST>::kScale h)
+template <int ST, bool kRaw = false>
 __device__ __forceinline__ void pull_cell(const SimDev& S, const GLB typename Store<ST>::T* src, int x, int y,
                                           int z, int64_t cell, RealOf<ST> h[kQ]) {
   using T = typename Store<ST>::T;
@@ -384,7 +400,8 @@ __device__ __forceinline__ void pull_cell(const SimDev& S, const GLB typename St
     const int plo = q < opp(q) ? q : opp(q);
     const uint32_t el = (uint32_t)(((layer >= 0 ? opp(q) : q) - plo) * (int)nc + sc);
     const GLB char* base = (const GLB char*)(src + (int64_t)plo * nc);
-    h[q] = Store<ST>::h((const GLB T*)(base + el * (uint32_t)sizeof(T)), 0, q);
+    const GLB T* at = (const GLB T*)(base + el * (uint32_t)sizeof(T));
+    h[q] = kRaw ? Store<ST>::h_raw(at) : Store<ST>::h(at, 0, q);
   }
 }
 

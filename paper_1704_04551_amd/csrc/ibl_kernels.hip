@@ -444,8 +444,14 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
           }
           continue;
         }
+        // the populations in their stored units, kS h (kS = 2^16 for FP16,
+        // else 1): the collision below works in them, with its weights scaled
+        // by kS and the moments unscaled once (a power-of-two scale commutes
+        // with every rounding, so this is bitwise the unscaled arithmetic)
+        constexpr double kS = Store<ST>::kScale;
+        auto wqs = [](int q) { return wq(q) * kS; };
         R h[kQ];
-        pull_cell<ST>(S, src, x, y, z, cell, h);
+        pull_cell<ST, true>(S, src, x, y, z, cell, h);
         // moments, Eq. (3), in type D (FP64 for FP64 / FP32 storage: exact sums
         // of the stored values): rho = sum f = 1 + sum h ; J = rho u = sum h c + g/2
         D drho = 0, jx = 0, jy = 0, jz = 0;
@@ -456,6 +462,13 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
           if (kCx[q]) jx += kCx[q] > 0 ? hq : -hq;
           if (kCy[q]) jy += kCy[q] > 0 ? hq : -hq;
           if (kCz[q]) jz += kCz[q] > 0 ? hq : -hq;
+        }
+        if constexpr (kS != 1.0) {
+          const D is = (D)(1.0 / kS);
+          drho *= is;
+          jx *= is;
+          jy *= is;
+          jz *= is;
         }
         R gix = (R)0, giy = (R)0, giz = (R)0;  // spread force g_IB
         if (ib) FA::get(gq, li, inv, gix, giy, giz);
@@ -516,10 +529,10 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
         // uniform plane base plus a 32-bit byte offset (as for the loads)
         auto store = [&](int q, D v, uint32_t r16) {
           GLB T* at = (GLB T*)((GLB char*)(dst + (int64_t)q * nc) + (uint32_t)cell * (uint32_t)sizeof(T));
-          if constexpr (MW) v += (D)slot_wall_term(S, q, x, y, z, (int)cell);
-          Store<ST>::put_sr(at, v, r16);
+          if constexpr (MW) v += (D)(slot_wall_term(S, q, x, y, z, (int)cell) * kS);
+          Store<ST>::put_raw_sr(at, v, r16);
         };
-        store(0, fma(om1, (D)h[0], (D)wq(0) * omd + (D)((R)wq(0) * C0)), rs);
+        store(0, fma(om1, (D)h[0], (D)wqs(0) * omd + (D)((R)wqs(0) * C0)), rs);
 #pragma unroll
         for (int q = 1; q < kQ; q += 2) {
           // c_q . v for c_q with components in {-1, 0, 1}: sums and differences only
@@ -531,8 +544,8 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
             return d;
           };
           const R cu = cdot(ux, uy, uz), cg = cdot(gxr, gyr, gzr);
-          const D E = (D)wq(q) * omd, O = ((D)wq(q) * om3) * cdot(Jx, Jy, Jz);
-          const R Ne = (R)wq(q) * fma(cu, fma(k45, cu, k9 * cg), C0), No = ((R)wq(q) * k3) * cg;
+          const D E = (D)wqs(q) * omd, O = ((D)wqs(q) * om3) * cdot(Jx, Jy, Jz);
+          const R Ne = (R)wqs(q) * fma(cu, fma(k45, cu, k9 * cg), C0), No = ((R)wqs(q) * k3) * cg;
           rs ^= rs << 13;
           rs ^= rs >> 17;
           rs ^= rs << 5;

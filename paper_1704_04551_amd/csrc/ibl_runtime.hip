@@ -431,11 +431,27 @@ __global__ void k_static_tables(StaticBatchArgs a, StaticBatchTables* t) {
 }
 static_assert(sizeof(SimDev) % 4 == 0, "descriptor copied as 32-bit words");
 
-// plain streaming copy (calibration): 16-byte elements, grid-stride
-__global__ __launch_bounds__(256) void k_hbm_copy(const uint4* __restrict__ src, uint4* __restrict__ dst,
+// plain streaming copy (calibration): 16-byte elements, four per thread in
+// flight (loads first, then stores; non-temporal, as the lattice kernel's
+// population traffic), grid-stride over blocks of 4 x 256 elements
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_hbm_copy(const u32x4* __restrict__ src, u32x4* __restrict__ dst,
                                                   int64_t n) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+  constexpr int kU = 4;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x * kU;
+  for (int64_t b = (int64_t)blockIdx.x * blockDim.x * kU + threadIdx.x; b < n; b += stride) {
+    u32x4 v[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int64_t i = b + (int64_t)k * blockDim.x;
+      if (i < n) v[k] = __builtin_nontemporal_load(src + i);
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      const int64_t i = b + (int64_t)k * blockDim.x;
+      if (i < n) __builtin_nontemporal_store(v[k], dst + i);
+    }
+  }
 }
 
 }  // namespace
@@ -449,13 +465,13 @@ ibl_status ibl_hbm_copy(const void* src, void* dst, size_t bytes, void* stream) 
     return fail(IBL_ERR_ARG, "copy: null buffer, or a size or address not a multiple of 16");
   const int64_t n = (int64_t)(bytes / 16);
   if (n == 0) return IBL_OK;
-  // 8 workgroups of 256 threads per compute unit, a multiple of the 8 XCDs
+  // up to 16 workgroups of 256 threads per compute unit
   int dev = 0, cus = 256;
   HIPCHK(hipGetDevice(&dev));
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int64_t need = (n + 255) / 256;
-  const int grid = (int)(need < 8LL * cus ? need : 8LL * cus);
-  hipLaunchKernelGGL(k_hbm_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const uint4*)src, (uint4*)dst, n);
+  const int64_t need = (n + 1023) / 1024;
+  const int grid = (int)(need < 16LL * cus ? need : 16LL * cus);
+  hipLaunchKernelGGL(k_hbm_copy, dim3(grid), dim3(256), 0, (hipStream_t)stream, (const u32x4*)src, (u32x4*)dst, n);
   HIPCHK(hipGetLastError());
   return IBL_OK;
 }
