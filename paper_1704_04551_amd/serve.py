@@ -131,7 +131,14 @@ class GpuBackend:
 
     def failed(self, sim) -> Optional[str]:
         st = sim.sync_status()
-        return None if st == 0 else {-4: "invalid state", -5: "unstable"}.get(st, "error %d" % st)
+        if st == 0:
+            return None
+        why = {-4: "invalid state", -5: "unstable"}.get(st, "error %d" % st)
+        try:  # the latched health bits (a rare path: one reduction)
+            why += " (health 0x%x)" % sim.conservation()[2]
+        except Exception:  # the reduction reports the same error: the bits stay unknown
+            pass
+        return why
 
     def result(self, sim, spec) -> dict:
         mass, mom, health = sim.conservation()
@@ -295,6 +302,8 @@ class Server:
             "peak_pool_bytes": self.peak_used,
             "chunks": self.chunks,
             "max_concurrent": self.max_concurrent,
+            "failed_reasons": dict(collections.Counter(str(j.failed) for j in self.failed)),
+            "rejected_reasons": dict(collections.Counter(str(j.rejected) for j in self.rejected)),
         }
 
     def close(self):
