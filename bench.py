@@ -519,7 +519,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"f32": "f32", "f16": "f16-offset storage, f32 compute", "f64": "f64"}[args.storage],
+        "dtype": {"f32": "f32", "f16": "f32", "f64": "f64"}[args.storage],  # arithmetic; storage in config
         "data": "synthetic (seeded RSA of Evans-Fung cells)",
         "config": {"workload": spec.name, "cells": cells, "capsules": len(spec.capsules),
                    "nodes": spec.nodes, "tau": spec.tau, "g_body": spec.g_body[0],
