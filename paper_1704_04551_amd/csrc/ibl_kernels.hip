@@ -40,16 +40,6 @@ __device__ __forceinline__ double rcp_r(double r) {
   return fma(i, fma(-r, i, 1.0), i);
 }
 
-// Wall term carried by the stored slot q of fluid cell (x, y, z): where
-// x + c_q is a wall layer, the slot is read back by the cell's own
-// bounce-back of direction opp(q), which adds 6 w_opp(q) (c_opp(q) . u_wall);
-// elsewhere 0.
-__device__ __forceinline__ double slot_wall_term(const SimDev& S, int q, int x, int y, int z, int cell) {
-  int layer;
-  (void)pull_source(S, opp(q), x, y, z, cell, layer);
-  return layer >= 0 ? S.bbw[opp(q)][layer] : 0.0;
-}
-
 // ------------------------------------------------------------------ init --
 template <int ST>
 __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
@@ -107,7 +97,7 @@ __device__ void init_cell(const SimDev& S, int x, int y, int z, int profile) {
   // stored populations are post-collision values that the first step's
   // pull turns into f_eq(1, u0): the one read by the consumer x + c_q, or,
   // where x + c_q is a wall layer, the bounce-back value of direction opp(q)
-  // at x itself (the slot carries its wall term, as the collision stores it)
+  // at x itself (the slot carries its wall term, as a step leaves it)
 #pragma unroll
   for (int q = 0; q < kQ; ++q) {
     int cn[3] = {x + kCx[q], y + kCy[q], z + kCz[q]};
@@ -290,9 +280,7 @@ struct FixAcc<double> {
 #define IBL_LATTICE_WAVES 5
 #endif
 constexpr int kLatticeWaves = IBL_LATTICE_WAVES;
-// MW: some simulation of the launch set has a moving wall (the stored
-// bounce-back slots carry a wall term; without moving walls every term is 0).
-template <int ST, bool MW>
+template <int ST>
 __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void k_lattice(const SimDev* __restrict__ sims,
                                                            Items it, int mode) {
   using T = typename Store<ST>::T;
@@ -526,31 +514,35 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
         rs *= 0x846ca68bu;
         rs ^= rs >> 16;
         rs |= 1u;  // a non-zero xorshift state
-        // uniform plane base plus a 32-bit byte offset (as for the loads)
-        auto store = [&](int q, D v, uint32_t r16) {
-          GLB T* at = (GLB T*)((GLB char*)(dst + (int64_t)q * nc) + (uint32_t)cell * (uint32_t)sizeof(T));
-          if constexpr (MW) v += (D)(slot_wall_term(S, q, x, y, z, (int)cell) * kS);
-          Store<ST>::put_raw_sr(at, v, r16);
-        };
-        store(0, fma(om1, (D)h[0], (D)wqs(0) * omd + (D)((R)wqs(0) * C0)), rs);
-#pragma unroll
-        for (int q = 1; q < kQ; q += 2) {
-          // c_q . v for c_q with components in {-1, 0, 1}: sums and differences only
-          auto cdot = [q](auto vx, auto vy, auto vz) {
-            decltype(vx) d = 0;
-            if (kCx[q]) d = kCx[q] > 0 ? vx : -vx;
-            if (kCy[q]) d = kCy[q] > 0 ? d + vy : d - vy;
-            if (kCz[q]) d = kCz[q] > 0 ? d + vz : d - vz;
-            return d;
+        // collision and stores (a moving wall's term is added to the slots
+        // next to it afterwards, by k_wall_slots)
+        {
+          uint32_t r = rs;
+          // uniform plane base plus a 32-bit byte offset (as for the loads)
+          auto store = [&](int q, D v, uint32_t r16) {
+            GLB T* at = (GLB T*)((GLB char*)(dst + (int64_t)q * nc) + (uint32_t)cell * (uint32_t)sizeof(T));
+            Store<ST>::put_raw_sr(at, v, r16);
           };
-          const R cu = cdot(ux, uy, uz), cg = cdot(gxr, gyr, gzr);
-          const D E = (D)wqs(q) * omd, O = ((D)wqs(q) * om3) * cdot(Jx, Jy, Jz);
-          const R Ne = (R)wqs(q) * fma(cu, fma(k45, cu, k9 * cg), C0), No = ((R)wqs(q) * k3) * cg;
-          rs ^= rs << 13;
-          rs ^= rs >> 17;
-          rs ^= rs << 5;
-          store(q, fma(om1, (D)h[q], (E + O) + (D)(Ne + No)), rs);
-          store(q + 1, fma(om1, (D)h[q + 1], (E - O) + (D)(Ne - No)), rs >> 16);
+          store(0, fma(om1, (D)h[0], (D)wqs(0) * omd + (D)((R)wqs(0) * C0)), r);
+#pragma unroll
+          for (int q = 1; q < kQ; q += 2) {
+            // c_q . v for c_q with components in {-1, 0, 1}: sums and differences only
+            auto cdot = [q](auto vx, auto vy, auto vz) {
+              decltype(vx) d = 0;
+              if (kCx[q]) d = kCx[q] > 0 ? vx : -vx;
+              if (kCy[q]) d = kCy[q] > 0 ? d + vy : d - vy;
+              if (kCz[q]) d = kCz[q] > 0 ? d + vz : d - vz;
+              return d;
+            };
+            const R cu = cdot(ux, uy, uz), cg = cdot(gxr, gyr, gzr);
+            const D E = (D)wqs(q) * omd, O = ((D)wqs(q) * om3) * cdot(Jx, Jy, Jz);
+            const R Ne = (R)wqs(q) * fma(cu, fma(k45, cu, k9 * cg), C0), No = ((R)wqs(q) * k3) * cg;
+            r ^= r << 13;
+            r ^= r >> 17;
+            r ^= r << 5;
+            store(q, fma(om1, (D)h[q], (E + O) + (D)(Ne + No)), r);
+            store(q + 1, fma(om1, (D)h[q + 1], (E - O) + (D)(Ne - No)), r >> 16);
+          }
         }
       }
     }
@@ -560,6 +552,69 @@ __global__ __launch_bounds__(kBrickThreads, ST == kF64 ? 1 : kLatticeWaves) void
       if ((tid & 63) == 0) atomicOr((unsigned*)S.health, bad);
     }
     if (ib) __syncthreads();  // the next brick clears the field
+  }
+}
+
+// ---------------------------------------------------------- moving walls --
+// Halfway bounce-back off a moving wall adds 6 w_i rho_w (c_i . u_wall) to the
+// population a fluid cell reflects.  The cell reads that population from its
+// own stored slot q (where x + c_q is a wall layer; it returns as opp(q)), so
+// the term is added to the slot once collide-stream has stored it: only the
+// cells of the layers next to the walls, each slot once (a slot meets exactly
+// one wall layer: the first wall axis of x, y, z that x + c_q crosses), in
+// the storage's arithmetic with a stochastically rounded store (random bits
+// from (cell, step, slot), a hash apart from the collision's).
+// Grid: x strides over a simulation's wall planes, y is the simulation.
+template <int ST>
+__global__ __launch_bounds__(256) void k_wall_slots(const SimDev* __restrict__ sims, Items it) {
+  using T = typename Store<ST>::T;
+  using D = typename Store<ST>::D;
+  constexpr double kS = Store<ST>::kScale;
+  const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, nt = (int64_t)gridDim.x * blockDim.x;
+  for (int si = blockIdx.y; si < it.nsim; si += gridDim.y) {
+    const SimDev& S = sims[si];
+    if (*S.remaining <= it.sub) continue;  // uniform
+    const int64_t stepn = *S.step + it.sub;
+    GLB T* dst = (GLB T*)S.f[(int)(stepn & 1) ^ 1];
+    const int64_t nc = S.ncell;
+    const int n[3] = {S.n[0], S.n[1], S.n[2]};
+    for (int a = 0; a < 3; ++a) {
+      if (!S.wall[a]) continue;  // uniform
+      const int b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;  // the plane's axes
+      const int64_t plane = (int64_t)n[b] * n[c];
+      for (int side = 0; side < 2; ++side) {
+        const int layer = 2 * a + side;
+        bool any = false;  // uniform: this wall moves
+        for (int q = 0; q < kQ; ++q) any |= S.bbw[q][layer] != 0.0;
+        if (!any) continue;
+        for (int64_t k = t0; k < plane; k += nt) {
+          int cc[3];
+          cc[a] = side ? n[a] - 2 : 1;
+          cc[b] = (int)(k % n[b]);
+          cc[c] = (int)(k / n[b]);
+          const int x = cc[0], y = cc[1], z = cc[2];
+          if (solid_cell(S, x, y, z)) continue;
+          const int64_t cell = x + (int64_t)n[0] * (y + (int64_t)n[1] * z);
+          const int want = side ? 1 : -1;  // c_q along a pointing into this wall
+#pragma unroll
+          for (int q = 1; q < kQ; ++q) {
+            if ((a == 0 ? kCx[q] : (a == 1 ? kCy[q] : kCz[q])) != want) continue;
+            int lq;  // the wall layer this slot meets (the first wall axis)
+            (void)pull_source(S, opp(q), x, y, z, (int)cell, lq);
+            if (lq != layer) continue;
+            GLB T* at = dst + (int64_t)q * nc + cell;
+            uint32_t r = (uint32_t)cell * 0x2C1B3C6Du + (uint32_t)stepn * 0x297A2D39u + (uint32_t)q * 0x9E3779B1u;
+            r ^= r >> 16;
+            r *= 0x7feb352du;
+            r ^= r >> 15;
+            r *= 0x846ca68bu;
+            r ^= r >> 16;
+            const D v = (D)Store<ST>::h_raw(at) + (D)(S.bbw[opp(q)][layer] * kS);
+            Store<ST>::put_raw_sr(at, v, r);
+          }
+        }
+      }
+    }
   }
 }
 
@@ -687,12 +742,11 @@ static void phase_impl(const SimDev* sims, const Items& it, int phase, int mode,
       launch_forces(ST, sims, it, mode, s);
       break;
     case kPhaseLattice:
-      if (it.moving_walls)
-        hipLaunchKernelGGL((k_lattice<ST, true>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s,
-                           sims, it, mode);
-      else
-        hipLaunchKernelGGL((k_lattice<ST, false>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s,
-                           sims, it, mode);
+      hipLaunchKernelGGL((k_lattice<ST>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s, sims,
+                         it, mode);
+      if (it.moving_walls && mode == 0)
+        hipLaunchKernelGGL((k_wall_slots<ST>), dim3(256, it.nsim < 65535 ? it.nsim : 65535), dim3(256), 0, s,
+                           sims, it);
       break;
     case kPhaseInterp:
       launch_interp(ST, sims, it, mode, s);

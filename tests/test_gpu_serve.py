@@ -62,7 +62,7 @@ def test_job_crossing_mach_bound_is_retired_as_failed():
         srv.close()
     print("serve stats", st)
     assert st["failed"] == 1 and st["finished"] == 1, st
-    assert jobs[0].failed == "unstable" and jobs[0].result is None
+    assert jobs[0].failed.startswith("unstable") and "0x4" in jobs[0].failed and jobs[0].result is None
     assert jobs[0].left == 600, jobs[0].left
     assert jobs[1].result["health"] == 0
 
