@@ -140,9 +140,10 @@ def cpu_baseline(spec, steps, storage, single_steps=1):
     return base, err
 
 
-def run_batched(storage, steps, skin):
+def run_batched(storage, steps, skin, plain_form=True):
     """Config of 64 uneven simulations: one batched launch sequence vs the
-    same simulations one after another (the plain form), at one list skin."""
+    same simulations one after another (the plain form, unless plain_form is
+    False), at one list skin."""
     import torch
     from paper_1704_04551_amd import ibl
     from paper_1704_04551_amd import workloads as W
@@ -160,6 +161,13 @@ def run_batched(storage, steps, skin):
     sims[0].sync()
     torch.cuda.synchronize()
     tb = time.perf_counter() - t0
+    if not plain_form:
+        B.close()
+        for s in sims:
+            s.close()
+        return {"sims": len(specs), "cells": cells, "steps_each": steps, "skin": skin,
+                "nodes": sum(s.nodes for s in specs),
+                "batched_mlups": round(cells * steps / tb / 1e6, 1), "batched_s": round(tb, 4)}, []
     plain = [ibl.Sim.from_spec(s, storage=storage, skin=skin) for s in specs]
     for p in plain:
         p.step(1)
@@ -397,6 +405,9 @@ def main():
     ap.add_argument("--skin", type=int, default=None, choices=[0, 1],
                     help="fixed candidate-list skin (skips the autotuner)")
     ap.add_argument("--batched-steps", type=int, default=500)
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the 64-simulation batched workload, without its plain form "
+                         "(its own JSON line; a profiling aid)")
     ap.add_argument("--membrane-steps", type=int, default=300, help="0 skips the full-membrane run")
     ap.add_argument("--serve-seconds", type=float, default=15.0, help="0 skips the served runs")
     ap.add_argument("--serve-rate", type=float, default=20.0)
@@ -453,6 +464,11 @@ def main():
         return
     if args.precision_sweep:
         precision_sweep(args)
+        return
+    if args.batched_only:
+        # the batched workload alone, at one skin (a profiling aid)
+        r, _ = run_batched(args.storage, args.batched_steps, args.skin or 0, plain_form=False)
+        print(json.dumps(r), flush=True)
         return
     if args.gpus != 1:
         print("bench.py: runs on one GPU only; --gpus %d is not supported "

@@ -120,6 +120,8 @@ struct SimDev {
   double uhi[3][3];
   double bbw[kQ][6];      // moving-wall term 6 w_q (c_q . u_wall) of a bounce-back link, per
                           // direction and wall layer (2 * axis + [hi side])
+  uint32_t wall_moving;   // bit l: wall layer l has a non-zero term (a moving wall axis)
+  uint32_t pad_wm;
   int32_t has_ib;         // 1 when meshes are present
   int32_t nnodes;
   int32_t nmeshes;
@@ -202,6 +204,7 @@ struct Items {
                              // 2: FP32 / FP16 storage through the edge-share LDS kernel
   int32_t membrane;          // 1 when some mesh has WLC-POW, area or volume terms
   int32_t moving_walls;      // 1 when some simulation has a wall layer with a non-zero velocity
+  int32_t wall_cells;        // the largest wall-adjacent layer (cells) of those simulations
   int32_t rigid;             // 1 when some mesh is a rigid body
   int32_t morse;             // 1 when some simulation has the Morse repulsion on
   const int32_t* lat_off;    // [nsim + 1]

@@ -584,9 +584,7 @@ __global__ __launch_bounds__(256) void k_wall_slots(const SimDev* __restrict__ s
       const int64_t plane = (int64_t)n[b] * n[c];
       for (int side = 0; side < 2; ++side) {
         const int layer = 2 * a + side;
-        bool any = false;  // uniform: this wall moves
-        for (int q = 0; q < kQ; ++q) any |= S.bbw[q][layer] != 0.0;
-        if (!any) continue;
+        if (!((S.wall_moving >> layer) & 1u)) continue;  // uniform: this wall does not move
         for (int64_t k = t0; k < plane; k += nt) {
           int cc[3];
           cc[a] = side ? n[a] - 2 : 1;
@@ -745,8 +743,8 @@ static void phase_impl(const SimDev* sims, const Items& it, int phase, int mode,
       hipLaunchKernelGGL((k_lattice<ST>), dim3(grid_for(it.lat_total, 1 << 22)), dim3(kBrickThreads), 0, s, sims,
                          it, mode);
       if (it.moving_walls && mode == 0)
-        hipLaunchKernelGGL((k_wall_slots<ST>), dim3(256, it.nsim < 65535 ? it.nsim : 65535), dim3(256), 0, s,
-                           sims, it);
+        hipLaunchKernelGGL((k_wall_slots<ST>), dim3((it.wall_cells + 255) / 256, it.nsim < 65535 ? it.nsim : 65535),
+                           dim3(256), 0, s, sims, it);
       break;
     case kPhaseInterp:
       launch_interp(ST, sims, it, mode, s);

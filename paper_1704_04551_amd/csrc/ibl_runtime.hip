@@ -353,8 +353,14 @@ ibl_status upload_simdev(ibl_sim S) {
   it.forces_variant = forces_variant();
   it.membrane = S->membrane;
   it.moving_walls = 0;
-  for (int q = 0; q < kQ; ++q)
-    for (int l = 0; l < 6; ++l) it.moving_walls |= S->hd.bbw[q][l] != 0.0;
+  it.wall_cells = 0;
+  for (int l = 0; l < 6; ++l) {
+    if (!((S->hd.wall_moving >> l) & 1u)) continue;
+    it.moving_walls = 1;
+    const int a = l / 2, b = a == 0 ? 1 : 0, c = a == 2 ? 1 : 2;
+    const int64_t plane = (int64_t)S->desc.n[b] * S->desc.n[c];
+    it.wall_cells = (int32_t)(plane > it.wall_cells ? plane : it.wall_cells);
+  }
   it.rigid = S->rigid;
   it.morse = S->hd.morse[0] != 0.0 ? 1 : 0;
   it.sub = 0;
@@ -531,6 +537,10 @@ ibl_status ibl_sim_create(const ibl_sim_desc* desc, void* dev_arena, size_t aren
         const double* uw = hi ? d.uhi[a] : d.ulo[a];
         d.bbw[q][2 * a + hi] = 6.0 * wq(q) * (kCx[q] * uw[0] + kCy[q] * uw[1] + kCz[q] * uw[2]);
       }
+  d.wall_moving = 0u;
+  for (int l = 0; l < 6; ++l)
+    for (int q = 0; q < kQ; ++q)
+      if (desc->wall[l / 2] && d.bbw[q][l] != 0.0) d.wall_moving |= 1u << l;
   d.ncell = L.ncell;
   d.nbrick = L.nbrick;
   d.delta = desc->delta;
@@ -1313,12 +1323,14 @@ ibl_status ibl_batch_create(const ibl_sim* sims, int32_t n, ibl_batch* out) {
   it.big_templates = 0;
   it.membrane = 0;
   it.moving_walls = 0;
+  it.wall_cells = 0;
   it.rigid = 0;
   it.morse = 0;
   for (int i = 0; i < n; ++i) {
     it.big_templates |= sims[i]->big_templates;
     it.membrane |= sims[i]->membrane;
     it.moving_walls |= sims[i]->items.moving_walls;
+    it.wall_cells = sims[i]->items.wall_cells > it.wall_cells ? sims[i]->items.wall_cells : it.wall_cells;
     it.rigid |= sims[i]->rigid;
     it.morse |= sims[i]->items.morse;
   }
@@ -1411,6 +1423,7 @@ ibl_status ibl_batch_step_static(const ibl_sim* sims, int32_t n, const int64_t* 
     it.big_templates |= sims[i]->big_templates;
     it.membrane |= sims[i]->membrane;
     it.moving_walls |= si.moving_walls;
+    it.wall_cells = si.wall_cells > it.wall_cells ? si.wall_cells : it.wall_cells;
     it.rigid |= sims[i]->rigid;
     it.morse |= si.morse;
   }
