@@ -528,9 +528,10 @@ __device__ __forceinline__ void fx_add(long long* p, long long v) {
   atomicAdd((unsigned long long*)p, (unsigned long long)v);
 }
 
-__global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __restrict__ sims, Items it, int mode) {
+__global__ __launch_bounds__(kFxThreads, 4) void k_forces_fx(const SimDev* __restrict__ sims, Items it, int mode) {
   static_assert(kFxBits == 40, "fx_quant and the readout scale by 2^40");
   __shared__ long long acc[3][kLdsNodes];
+  __shared__ double xs[3][kLdsNodes];  // the capsule's positions, read once
   __shared__ BinTable bt;
   __shared__ uint32_t wmax;
   const int tid = threadIdx.x;
@@ -550,16 +551,32 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
     const ListStep L = list_step(S, it, mode);
     clear_next_rebuild(S, L, m, mode);
     if (S.mesh_rigid[m]) continue;  // a rigid body (k_rigid_nodes); uniform
-    for (int i = tid; i < nn; i += kFxThreads) acc[0][i] = acc[1][i] = acc[2][i] = 0;
+    for (int i = tid; i < nn; i += kFxThreads) {
+      acc[0][i] = acc[1][i] = acc[2][i] = 0;
+      xs[0][i] = X0[i];
+      xs[1][i] = X0[ms + i];
+      xs[2][i] = X0[2 * ms + i];
+    }
+    // each edge's four vertices (16 bytes), loaded one edge ahead: the edge
+    // loop then waits on LDS only
+    const GLB int4* ev4 = (const GLB int4*)(S.ev + 4 * e0);
+    int4 nxt;
+    nxt.x = nxt.y = nxt.z = nxt.w = 0;
+    if (tid < ne) {
+      const int4 t = ev4[tid];
+      nxt = t;
+    }
     __syncthreads();
     for (int e = tid; e < ne; e += kFxThreads) {
-      const GLB int* v = S.ev + 4 * (e0 + e);
-      int vk[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) vk[k] = v[k];
+      const int4 cur = nxt;
+      if (e + kFxThreads < ne) {
+        const int4 t = ev4[e + kFxThreads];
+        nxt = t;
+      }
+      const int vk[4] = {cur.x, cur.y, cur.z, cur.w};
       D3 p[4];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) p[k] = {X0[vk[k]], X0[ms + vk[k]], X0[2 * ms + vk[k]]};
+      for (int k = 0; k < 4; ++k) p[k] = {xs[0][vk[k]], xs[1][vk[k]], xs[2][vk[k]]};
       D3 G0, G3, F1;
       edge_forces(p[0], p[1], p[2], p[3], S.el0[e0 + e], S.ec0[e0 + e], S.es0[e0 + e], ks, kb, G0, G3, F1);
       const double g0[3] = {G0.x, G0.y, G0.z}, g3[3] = {G3.x, G3.y, G3.z}, f1[3] = {F1.x, F1.y, F1.z};
@@ -582,7 +599,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           F[a] = act ? (double)acc[a][i] * 0x1p-40 : 0.0;
-          Xp[a] = act ? X0[a * ms + i] : 0.0;
+          Xp[a] = act ? xs[a][i] : 0.0;
         }
         add_membrane_terms(S, it, m, act, off + i, F);
         emit_nodes<float>(S, bt, L, act, off + i, Xp, F, mode, fbits);
@@ -593,7 +610,7 @@ __global__ __launch_bounds__(kFxThreads, 5) void k_forces_fx(const SimDev* __res
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           F[a] = (double)acc[a][i] * 0x1p-40;
-          Xp[a] = X0[a * ms + i];
+          Xp[a] = xs[a][i];
         }
         add_membrane_terms(S, it, m, true, off + i, F);
         emit_node<float>(S, L, off + i, Xp, F, mode, fbits);
