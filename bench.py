@@ -289,20 +289,8 @@ def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
 
 
 def tile_spec(spec, reps=(2, 2, 2)):
-    """The cells of `spec` repeated reps[a] times along each axis (every copy
-    keeps its wall clearance, so copies never overlap)."""
     from paper_1704_04551_amd import workloads as W
-    n = tuple(spec.n[a] * reps[a] for a in range(3))
-    caps = []
-    for kz in range(reps[2]):
-        for ky in range(reps[1]):
-            for kx in range(reps[0]):
-                sh = np.array([kx * spec.n[0], ky * spec.n[1], kz * spec.n[2]], float)
-                for c in spec.capsules:
-                    caps.append(W.Capsule(c.x + sh, c.x_ref + sh, c.tris, c.ks, c.kb, c.shape_key))
-    return W.SimSpec(n=n, tau=spec.tau, g_body=spec.g_body, wall=spec.wall, delta=spec.delta,
-                     capsules=caps, steps=spec.steps, seed=spec.seed,
-                     name="rbc-channel-%dx%dx%d-tiled" % n)
+    return W.tiled(spec, reps)
 
 
 def precision_sweep(args):

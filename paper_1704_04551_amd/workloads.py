@@ -291,6 +291,23 @@ def config_rbc_channel(n=(256, 128, 128), count=1100, diameter=16.0, seed=1002, 
                    name="rbc-channel-%dx%dx%d" % tuple(n))
 
 
+def tiled(spec: SimSpec, reps=(2, 2, 2)) -> SimSpec:
+    """The cells of `spec` repeated reps[a] times along each axis (every copy
+    keeps its wall clearance, so copies never overlap): the 512x256x256
+    channel of the precision study is the seeded 256x128x128 layout tiled
+    2x2x2."""
+    n = tuple(spec.n[a] * reps[a] for a in range(3))
+    caps = []
+    for kz in range(reps[2]):
+        for ky in range(reps[1]):
+            for kx in range(reps[0]):
+                sh = np.array([kx * spec.n[0], ky * spec.n[1], kz * spec.n[2]], float)
+                for c in spec.capsules:
+                    caps.append(Capsule(c.x + sh, c.x_ref + sh, c.tris, c.ks, c.kb, c.shape_key))
+    return SimSpec(n=n, tau=spec.tau, g_body=spec.g_body, wall=spec.wall, delta=spec.delta,
+                   capsules=caps, steps=spec.steps, seed=spec.seed, name="rbc-channel-%dx%dx%d-tiled" % n)
+
+
 def config_poiseuille(n=(64, 64, 256), tau=0.8, g=1e-6, axis=2, wall_axis=0, steps=1000) -> SimSpec:
     """Plane Poiseuille channel without cells: flow along `axis` (periodic),
     walls on `wall_axis`, body force g."""

@@ -8,10 +8,12 @@ Bars: FP32 storage 1e-5, FP16-offset storage 1e-3, for the fluid velocity
 (max-norm of the difference relative to max |u_ref|, fluid cells) and for the
 node positions (max |dX| relative to the largest displacement).
 
-The populations are stored in reduced precision, the collision is computed in
-FP64 and each store is rounded stochastically (unbiased), FP16 offsets scaled
-by 2^16.  This file is collected after the parity tests, so a miss here
-cannot hide them.
+The populations are stored in reduced precision with stochastically rounded
+(unbiased) stores: FP32 storage with the moments and the O(u) part of the
+collision in FP64, FP16 offsets scaled by 2^16 with FP32 arithmetic.  The
+full-size channel of the precision study (512x256x256) is checked over two
+steps.  This file is collected after the parity tests, so a miss here cannot
+hide them.
 """
 import time
 
@@ -73,3 +75,31 @@ def test_crop_64_channel_1000_steps(storage, crop_reference, capsys_module):
                   % (storage, eu_max, eu_l2, ex_abs, ex_rel))
     assert eu_max < BAR[storage], (storage, eu_max)
     assert ex_rel < BAR[storage], (storage, ex_rel)
+
+
+@pytest.mark.timeout(900)
+def test_precision_channel_512_full_size(capsys_module):
+    """The precision study's full-size channel (512x256x256, the seeded
+    256x128x128 layout tiled 2x2x2: 8144 cells, 5.2M nodes) in the bench's
+    launch configuration: after two steps, u and X against the FP64 oracle
+    within the FP32 bar and, for FP16-offset storage, within its bar."""
+    spec = W.tiled(W.config_rbc_channel())
+    assert spec.n == (512, 256, 256) and len(spec.capsules) == 8144
+    o = oracle_from_spec(spec)
+    o.step(2)
+    _, uo, _ = o.observe()
+    Xo = [o.nodes(m)[0] for m in range(len(spec.capsules))]
+    o.close()
+    capsys_module("512 oracle: 2 steps done")
+    mask = fluid_mask(spec)
+    for storage, tol in (("f32", 1e-5), ("f16", 1e-3)):
+        g = ibl.Sim.from_spec(spec, storage=storage, brick_x=64)
+        g.step(2)
+        g.sync()
+        _, ug, _ = g.fields(rho=False, g=False)
+        umax, ul2 = field_err(ug, uo, mask)
+        xr = max(node_err(g.nodes(m)[0], Xo[m], c.x)[1] for m, c in enumerate(spec.capsules))
+        g.close()
+        capsys_module("512 %s: u max %.3e L2 %.3e, X %.3e of the displacement" % (storage, umax, ul2, xr))
+        assert umax < tol, (storage, umax)
+        assert xr < tol, (storage, xr)
