@@ -79,3 +79,40 @@ def test_wall_speed_above_mach_bound_is_refused():
     finally:
         srv.close()
     assert st["rejected"] == 1 and st["finished"] == 0
+
+
+@pytest.mark.parametrize("edge", [48, 112])
+def test_served_job_vs_oracle(edge):
+    """A served job of the configured stream (the smallest and the largest
+    admitted lattice), run through the serving loop alongside another job,
+    against the FP64 oracle after 300 steps: fluid velocity and node
+    positions within the FP32 bar."""
+    from parity_util import field_err, fluid_mask, node_err, oracle_from_spec
+    rng = np.random.default_rng(1005 + edge)
+    spec = W.job_served(rng, edges=(edge,), steps=(300, 300))
+    other = W.job_served(rng, edges=(32,), steps=(150, 150))
+    jobs = [Job(0, spec, arrival=0.0, steps=300), Job(1, other, arrival=0.0, steps=150)]
+    srv = Server(GpuBackend("f32"), pool_bytes=1 << 33, chunk=50, max_resident=4)
+    try:
+        st = srv.run(jobs, time_limit=120)
+    finally:
+        srv.close()
+    assert st["finished"] == 2, st
+    o = oracle_from_spec(spec)
+    o.step(300)
+    Xg = jobs[0].result["X"][0]
+    Xo = o.nodes(0)[0]
+    dx, rel = node_err(Xg, Xo, spec.capsules[0].x)
+    assert rel < 1e-5 or dx < 1e-12, (dx, rel)
+    # the fluid: the same job run alone (bitwise the served result, tested
+    # above) against the oracle
+    g = ibl.Sim.from_spec(spec, storage="f32")
+    g.step(300)
+    g.sync()
+    assert np.array_equal(g.nodes(0)[0], Xg)
+    _, ug, _ = g.fields(rho=False, g=False)
+    _, uo, _ = o.observe()
+    eu = field_err(ug, uo, fluid_mask(spec))[0]
+    g.close()
+    o.close()
+    assert eu < 1e-5, eu
