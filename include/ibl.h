@@ -225,9 +225,12 @@ ibl_status ibl_mesh_membrane(ibl_sim sim, int32_t mesh, double kbt_p, double kg,
  * by minimum image on periodic axes.  Its force on each node is added to the
  * membrane force before spreading.  D0 = 0 turns it off.  Neighbours are
  * found on a grid of cells at least 2 lattice units wide, at most 48 nodes per
- * cell (IBL_HEALTH_OVERFLOW beyond); pair forces are summed per node in 64-bit
- * fixed point (2^-44 lattice units), so the sums are reproducible and the
- * pair forces cancel exactly.  Errors: IBL_ERR_ARG (negative or non-finite
+ * cell (IBL_HEALTH_OVERFLOW beyond); pair forces are summed per node in
+ * two-word 64-bit fixed point (units 2^-44 and 2^-96 lattice units: exact to
+ * 2^-96 per pair), so the sums are reproducible and the pair forces cancel
+ * exactly; a pair force component beyond 128 sets IBL_HEALTH_FORCE_RANGE and
+ * is clamped.  Set before ibl_batch_create on a batch holding the
+ * simulation.  Errors: IBL_ERR_ARG (negative or non-finite
  * D0, alpha <= 0, rc <= 0), IBL_ERR_UNSUPPORTED (rc > 2 lattice units, or a
  * simulation created with morse = 0). */
 ibl_status ibl_sim_morse(ibl_sim sim, double D0, double alpha, double r0, double rc);
