@@ -258,17 +258,22 @@ def run_served(storage, seconds, rate, step_scale, skin, seed=1005):
 #   kv = 2.2 N/m^2 / (1e-7 N / (0.5 um)^2) = 5.5e-6.
 FULL_MEMBRANE = (1.435e-5, 1.05e-3, 1.05e-3, 5.5e-6)  # kBT/p, kg, kl, kv
 FULL_MEMBRANE_KB = 4.6e-6
+# The Morse repulsion of Eq. (13) with the same table's constants, r read in
+# um and alpha in 1/um: D0 = 1.2e-18 J / (1e-7 N x 0.5 um) = 2.4e-5;
+# alpha = 0.5 / um = 0.25 / lu; r0 = rc = 0.66 um = 1.32 lu.
+PAPER_MORSE = (2.4e-5, 0.25, 1.32, 1.32)  # D0, alpha, r0, rc
 
 
 def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
     """The same workload with the paper's whole membrane energy and its red
     blood cell constants: WLC-POW stretching in place of the linear springs,
-    the dihedral bending, and the global / local area and volume constraints.  Graph-replayed steps timed
-    like the headline, then a phase-by-phase run."""
+    the dihedral bending, the global / local area and volume constraints, and
+    the Morse repulsion between cells.  Graph-replayed steps timed like the
+    headline, then a phase-by-phase run."""
     import dataclasses
     from paper_1704_04551_amd import ibl
     caps = [dataclasses.replace(c, ks=0.0, kb=FULL_MEMBRANE_KB, membrane=FULL_MEMBRANE) for c in spec.capsules]
-    sp = dataclasses.replace(spec, capsules=caps)
+    sp = dataclasses.replace(spec, capsules=caps, morse=PAPER_MORSE)
     sim = ibl.Sim.from_spec(sp, storage=storage, device="cuda:0", brick_x=brick_x, skin=skin)
     try:
         sim.step(warmup)
@@ -283,6 +288,7 @@ def run_full_membrane(spec, storage, brick_x, skin, steps, warmup):
     finally:
         sim.close()
     return {"terms": dict(zip(("kbt_p", "kg", "kl", "kv"), FULL_MEMBRANE)), "ks": 0.0, "kb": FULL_MEMBRANE_KB,
+            "morse": dict(zip(("D0", "alpha", "r0", "rc"), PAPER_MORSE)),
             "constants": "the paper's red blood cell values in lattice units", "steps": steps,
             "mlups": round(spec.cells * steps / wall / 1e6, 1), "ms_per_step": round(wall * 1e3 / steps, 4),
             "phase_ms": {k: round(v, 5) for k, v in phases.items()}, "health": health}

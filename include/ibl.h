@@ -125,7 +125,9 @@ typedef struct {
                               at the last build.  A tuning knob: results are bitwise
                               identical either way. */
   int32_t morse;           /* 1: reserve the neighbour grid of the inter-capsule Morse
-                              repulsion (ibl_sim_morse); 0: none */
+                              repulsion (ibl_sim_morse), (n/2)^3 cells of at least 2
+                              lattice units, at most 2^31 of them (IBL_ERR_ARG
+                              beyond); 0: none */
 } ibl_sim_desc;
 
 typedef struct ibl_sim_s* ibl_sim;

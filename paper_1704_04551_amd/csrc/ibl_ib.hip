@@ -900,23 +900,40 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
 // (which add the result to each node's membrane force):
 //   k_morse_bin    every capsule node into the neighbour grid of its step
 //                  parity (cells at least 2 lattice units wide, so every pair
-//                  closer than rc <= 2 lies in neighbouring cells); the
-//                  workgroups also empty the other parity's grid, used by the
-//                  previous step.
-//   k_morse_force  per node: the pair forces from the nodes of other capsules
-//                  in the 27 neighbouring cells, F = 2 alpha D0 (e^{-2 alpha
-//                  (r - r0)} - e^{-alpha (r - r0)}) (X_i - X_j) / r for r < rc,
-//                  each split into two 64-bit fixed-point words (units 2^-44
-//                  and 2^-96) and summed as integers: the sum is exact to
-//                  2^-96 per pair and does not depend on the order of the cell
-//                  lists, and the two nodes of a pair get exact opposites.
+//                  closer than rc <= 2 lies in neighbouring cells).  One
+//                  workgroup per capsule groups its nodes by cell in LDS and
+//                  reserves each group's range with one device atomic; each
+//                  cell also records its owner: 0 empty, m + 1 when it holds
+//                  only capsule m's nodes, -1 when it holds several capsules'
+//                  (the final value does not depend on the order of the
+//                  appends).  The workgroups also empty the other parity's
+//                  grid, used by the previous step.
+//   k_morse_force  one workgroup per capsule.  Each node marks its
+//                  neighbouring cells that hold other capsules' nodes (inside
+//                  a membrane nearly every cell is the capsule's own); the
+//                  workgroup stages the nodes of the marked cells (ids, then
+//                  positions and capsules, every load of a round in flight
+//                  together) in LDS, and each node sums its pair forces from
+//                  there: F = 2 alpha D0 (e^{-2 alpha (r - r0)} -
+//                  e^{-alpha (r - r0)}) (X_i - X_j) / r for r < rc, each split
+//                  into two 64-bit fixed-point words (units 2^-44 and 2^-96)
+//                  and summed as integers: the sum is exact to 2^-96 per pair
+//                  and does not depend on the order of the cell lists, and the
+//                  two nodes of a pair get exact opposites.  A capsule whose
+//                  marked cells overflow the LDS stage reads them from global
+//                  memory node by node instead (the same pairs and sums).
 //   k_morse_clear  an observation's grid, emptied after it (the next step
 //                  bins into the same parity).
 constexpr int kMorseThreads = 256;
-constexpr int kMorseChunks = 4;         // workgroups per capsule
-constexpr double kMorseHi = 0x1p44;     // unit of the high fixed-point word
-constexpr double kMorseLo = 0x1p52;     // unit of the low word, relative to the high one
-constexpr double kMorseLimit = 128.0;   // |pair force component| limit (health bit beyond)
+constexpr int kMorseSlots = 512;         // LDS table of a capsule's cells (power of two)
+constexpr int kMorseRound = 4;           // nodes per thread per binning round
+constexpr int kMorseStage = 1024;        // other capsules' nodes staged per capsule
+constexpr int kMorseNodes = 1024;        // capsule nodes of the staged path
+constexpr int kMorseBatch = 4;           // entries per batch of loads (direct path)
+constexpr double kMorseHi = 0x1p44;      // unit of the high fixed-point word
+constexpr double kMorseLo = 0x1p52;      // unit of the low word, relative to the high one
+constexpr double kMorseLimit = 128.0;    // |pair force component| limit (health bit beyond)
+static_assert(kMorseWords == 2, "grid cell words: owner, count");
 
 __device__ __forceinline__ int morse_axis(const SimDev& S, int a, double X) {
   const int n = S.n[a], ng = S.ngm[a];
@@ -925,36 +942,104 @@ __device__ __forceinline__ int morse_axis(const SimDev& S, int a, double X) {
   return c < 0 ? 0 : (c >= ng ? ng - 1 : c);
 }
 
+__device__ __forceinline__ int morse_cell_of(const SimDev& S, const double X[3]) {
+  return morse_axis(S, 0, X[0]) + S.ngm[0] * (morse_axis(S, 1, X[1]) + S.ngm[1] * morse_axis(S, 2, X[2]));
+}
+
+// LDS hash slot of a cell (inserted on first use); -1 when the table is full
+__device__ int morse_slot(int* key, int cell) {
+  int h = (int)(((uint32_t)cell * 2654435761u) >> 23) & (kMorseSlots - 1);
+  for (int p = 0; p < kMorseSlots; ++p) {
+    const int cur = atomicCAS(&key[h], -1, cell);
+    if (cur == -1 || cur == cell) return h;
+    h = (h + 1) & (kMorseSlots - 1);
+  }
+  return -1;
+}
+
+// slot of a cell already in the table
+__device__ __forceinline__ int morse_find(const int* key, int cell) {
+  int h = (int)(((uint32_t)cell * 2654435761u) >> 23) & (kMorseSlots - 1);
+  for (int p = 0; p < kMorseSlots && key[h] != cell; ++p) h = (h + 1) & (kMorseSlots - 1);
+  return h;
+}
+
+// a cell's owner after a node of capsule m joined it
+__device__ __forceinline__ void morse_own(GLB int32_t* w, int m) {
+  const int own = atomicCAS((int*)&w[0], 0, m + 1);
+  if (own != 0 && own != m + 1) atomicExch((int*)&w[0], -1);
+}
+
 __global__ __launch_bounds__(kMorseThreads) void k_morse_bin(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ int key[kMorseSlots], cnt[kMorseSlots], base[kMorseSlots];
   const int tid = threadIdx.x;
-  for (int item = xcd_block(); item < it.mesh_total * kMorseChunks; item += gridDim.x) {
-    const int mi = item / kMorseChunks, c = item % kMorseChunks;
-    const int s = find_sim(it.mesh_off, it.nsim, mi);
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     if (S.morse[0] == 0.0) continue;
-    const int m = mi - it.mesh_off[s];
+    const int m = item - it.mesh_off[s];
     const int par = (int)((*S.step + it.sub) & 1);
     if (mode == 0) {
       // empty the previous step's grid: this simulation's workgroups share it out
-      const int64_t nwg = (int64_t)(it.mesh_off[s + 1] - it.mesh_off[s]) * kMorseChunks;
-      const int64_t wg = (int64_t)m * kMorseChunks + c;
-      GLB int32_t* old = S.gcount + (int64_t)(par ^ 1) * S.ngrid;
-      for (int64_t k = wg * kMorseThreads + tid; k < S.ngrid; k += nwg * kMorseThreads) old[k] = 0;
+      const int64_t nwg = it.mesh_off[s + 1] - it.mesh_off[s];
+      GLB int32_t* old = S.gcount + (int64_t)(par ^ 1) * kMorseWords * S.ngrid;
+      for (int64_t k = m * (int64_t)kMorseThreads + tid; k < kMorseWords * S.ngrid; k += nwg * kMorseThreads)
+        old[k] = 0;
     }
     if (S.mesh_rigid[m]) continue;  // uniform: bodies take no part
     const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
     const int64_t ms = (int64_t)S.maxn;
-    for (int i = c * kMorseThreads + tid; i < nn; i += kMorseThreads * kMorseChunks) {
-      const int gid = off + i;
-      const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
-      if (!(isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2]))) continue;
-      const int64_t cell = morse_axis(S, 0, X[0]) +
-                           (int64_t)S.ngm[0] * (morse_axis(S, 1, X[1]) + (int64_t)S.ngm[1] * morse_axis(S, 2, X[2]));
-      const int64_t g = (int64_t)par * S.ngrid + cell;
-      const int pos = atomicAdd((int*)&S.gcount[g], 1);
-      if (pos < kMorseCap) S.glist[g * kMorseCap + pos] = gid;
-      else atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
+    GLB int32_t* gw = S.gcount + (int64_t)par * kMorseWords * S.ngrid;  // (owner, count) per cell
+    GLB int32_t* gl = S.glist + (int64_t)par * S.ngrid * kMorseCap;
+    for (int i0 = 0; i0 < nn; i0 += kMorseThreads * kMorseRound) {  // uniform
+      for (int k = tid; k < kMorseSlots; k += kMorseThreads) {
+        key[k] = -1;
+        cnt[k] = 0;
+      }
+      __syncthreads();
+      // the round's nodes join their cells' groups
+      int cell[kMorseRound], slot[kMorseRound], rank[kMorseRound];
+#pragma unroll
+      for (int u = 0; u < kMorseRound; ++u) {
+        const int i = i0 + u * kMorseThreads + tid;
+        cell[u] = -1;
+        slot[u] = -1;
+        rank[u] = 0;
+        if (i < nn) {
+          const int gid = off + i;
+          const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+          if (isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2])) {
+            cell[u] = morse_cell_of(S, X);
+            slot[u] = morse_slot(key, cell[u]);
+            if (slot[u] >= 0) rank[u] = atomicAdd(&cnt[slot[u]], 1);
+          }
+        }
+      }
+      __syncthreads();
+      // one reservation per group, and the owner
+      for (int k = tid; k < kMorseSlots; k += kMorseThreads)
+        if (key[k] >= 0) {
+          GLB int32_t* w = gw + kMorseWords * (int64_t)key[k];
+          base[k] = atomicAdd((int*)&w[1], cnt[k]);
+          morse_own(w, m);
+        }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < kMorseRound; ++u) {
+        if (cell[u] < 0) continue;
+        int pos;
+        if (slot[u] >= 0) {
+          pos = base[slot[u]] + rank[u];
+        } else {  // the table was full: this node appends alone
+          GLB int32_t* w = gw + kMorseWords * (int64_t)cell[u];
+          pos = atomicAdd((int*)&w[1], 1);
+          morse_own(w, m);
+        }
+        if (pos < kMorseCap) gl[(int64_t)cell[u] * kMorseCap + pos] = off + i0 + u * kMorseThreads + tid;
+        else atomicOr((unsigned*)S.health, (uint32_t)kHOverflow);
+      }
+      __syncthreads();  // the table is cleared for the next round
     }
   }
 }
@@ -973,73 +1058,290 @@ __device__ __forceinline__ void morse_accumulate(const SimDev& S, double v, long
   lo += __double2ll_rn((t - (double)h) * kMorseLo);
 }
 
-__global__ __launch_bounds__(kMorseThreads) void k_morse_force(const SimDev* __restrict__ sims, Items it, int mode) {
-  const int tid = threadIdx.x;
-  for (int item = xcd_block(); item < it.mesh_total * kMorseChunks; item += gridDim.x) {
-    const int mi = item / kMorseChunks, c = item % kMorseChunks;
-    const int s = find_sim(it.mesh_off, it.nsim, mi);
+// Constants of the pair force of one simulation
+struct MorseParams {
+  double D0, al, r0, rc;
+  double rc2;    // a bound on r^2 above every r that rounds below rc (the exact test follows)
+  double qn[3];  // a quarter of each period
+};
+__device__ __forceinline__ MorseParams morse_params(const SimDev& S) {
+  MorseParams P;
+  P.D0 = S.morse[0];
+  P.al = S.morse[1];
+  P.r0 = S.morse[2];
+  P.rc = S.morse[3];
+  P.rc2 = P.rc * P.rc * (1.0 + 0x1p-40);
+  for (int a = 0; a < 3; ++a) P.qn[a] = 0.25 * S.n[a];
+  return P;
+}
+
+// the pair force on the node at X from the node at Y, into the sums
+__device__ __forceinline__ void morse_pair(const SimDev& S, const MorseParams& P, const double X[3],
+                                           double y0, double y1, double y2, long long wh[3], long long wl[3]) {
+  const double Y[3] = {y0, y1, y2};
+  double d[3], r2 = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d[a] = X[a] - Y[a];
+    // minimum image; within a quarter period the image term is exactly zero,
+    // so the division is skipped
+    if (!S.wall[a] && !(fabs(d[a]) <= P.qn[a])) d[a] -= (double)S.n[a] * floor(d[a] / (double)S.n[a] + 0.5);
+    r2 += d[a] * d[a];
+  }
+  if (!(r2 <= P.rc2)) return;  // beyond the cutoff (taken before the square root)
+  const double r = sqrt(r2);
+  if (!(r < P.rc) || r == 0.0) return;
+  const double e1 = exp(-P.al * (r - P.r0)), f = 2.0 * P.al * P.D0 * (e1 * e1 - e1) / r;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) morse_accumulate(S, f * d[a], wh[a], wl[a]);
+}
+
+// The 27 neighbouring cells of a node's cell (each once; wrapped on periodic
+// axes; entries past an axis's count repeat its first cell).
+struct MorseCells {
+  int cl[3][3], cnt[3];
+};
+__device__ __forceinline__ void morse_cells(const SimDev& S, const double X[3], MorseCells& C) {
+  for (int a = 0; a < 3; ++a) {
+    const int ca = morse_axis(S, a, X[a]), ng = S.ngm[a];
+    int lo;
+    if (ng < 3) {
+      lo = 0;  // every cell once
+      C.cnt[a] = ng;
+    } else if (S.wall[a]) {
+      lo = ca > 0 ? ca - 1 : 0;
+      C.cnt[a] = (ca + 1 < ng ? ca + 1 : ng - 1) - lo + 1;
+    } else {
+      lo = ca - 1;
+      C.cnt[a] = 3;
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int v = lo + k;
+      C.cl[a][k] = k >= C.cnt[a] ? lo : (v < 0 ? v + ng : (v >= ng ? v - ng : v));
+    }
+  }
+}
+// (selected without indexing the arrays at a run-time position, which would
+// put them in scratch memory)
+__device__ __forceinline__ int morse_pick(const int v[3], int i) { return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]); }
+__device__ __forceinline__ int morse_cell(const SimDev& S, const MorseCells& C, int k) {
+  return morse_pick(C.cl[0], k % 3) + S.ngm[0] * (morse_pick(C.cl[1], (k / 3) % 3) + S.ngm[1] * morse_pick(C.cl[2], k / 9));
+}
+
+// Bits k = kx + 3 ky + 9 kz of the neighbouring cells that hold other
+// capsules' nodes (work), and of those holding several capsules' (mixed).
+// The owners are loaded a layer of nine at a time.
+__device__ __forceinline__ void morse_marks(const SimDev& S, const GLB int32_t* gw, const MorseCells& C, int m,
+                                            uint32_t& work, uint32_t& mixed) {
+  work = mixed = 0u;
+#pragma unroll 1
+  for (int kz = 0; kz < 3; ++kz) {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int bit = 9 * kz + k, kx = k % 3, ky = k / 3;
+      const int own = gw[kMorseWords * (int64_t)morse_cell(S, C, bit)];
+      const bool in = kx < C.cnt[0] && ky < C.cnt[1] && kz < C.cnt[2];
+      work |= (in && own != 0 && own != m + 1) ? 1u << bit : 0u;
+      mixed |= own < 0 ? 1u << bit : 0u;
+    }
+  }
+}
+
+// the two-word sums as the node's force
+__device__ __forceinline__ void morse_store(const SimDev& S, int gid, const long long wh[3], const long long wl[3]) {
+  const int64_t ms = (int64_t)S.maxn;
+  for (int a = 0; a < 3; ++a) {
+    // carry the low word's whole multiples of 2^-44 into the high one; both
+    // words then convert exactly while |F| < 2^9
+    const long long c = wl[a] >> 52;
+    const long long h = wh[a] + c, l = wl[a] - (c << 52);
+    S.Fm[a * ms + gid] = (double)h / kMorseHi + (double)l / (kMorseHi * kMorseLo);
+  }
+}
+
+// One node's pair forces read from global memory (capsules whose marked cells
+// do not fit the LDS stage).
+__device__ void morse_node_direct(const SimDev& S, const MorseParams& P, const GLB int32_t* gw,
+                                  const GLB int32_t* gl, int m, int gid) {
+  const int64_t ms = (int64_t)S.maxn;
+  const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+  long long wh[3] = {0, 0, 0}, wl[3] = {0, 0, 0};
+  if (isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2])) {
+    MorseCells C;
+    morse_cells(S, X, C);
+    uint32_t work, mixed;
+    morse_marks(S, gw, C, m, work, mixed);
+    while (work) {
+      const int kc = __builtin_ctz(work);
+      work &= work - 1u;
+      const int64_t cell = morse_cell(S, C, kc);
+      const bool mix = (mixed >> kc) & 1u;
+      const int c0 = gw[kMorseWords * cell + 1];
+      const int nc = c0 < kMorseCap ? c0 : kMorseCap;
+      const GLB int32_t* ce = gl + cell * kMorseCap;
+      for (int k0 = 0; k0 < nc; k0 += kMorseBatch) {
+        int jb[kMorseBatch];
+#pragma unroll
+        for (int t = 0; t < kMorseBatch; ++t) jb[t] = k0 + t < nc ? ce[k0 + t] : -1;
+#pragma unroll
+        for (int t = 0; t < kMorseBatch; ++t) {
+          if (jb[t] < 0) continue;
+          const int j = jb[t];
+          if (mix && S.node_mesh[j] == m) continue;  // the same capsule
+          morse_pair(S, P, X, S.X[j], S.X[ms + j], S.X[2 * ms + j], wh, wl);
+        }
+      }
+    }
+  }
+  morse_store(S, gid, wh, wl);
+}
+
+struct MorseStageLds {
+  int key[kMorseSlots];    // marked cells (-1: free)
+  int start[kMorseSlots];  // first staged entry of each (entries: up to the next start)
+  double x[3][kMorseStage];
+  int mesh[kMorseStage];
+  uint32_t work[kMorseNodes];  // each node's marked neighbour cells
+  int16_t wlist[kMorseNodes];  // the nodes that have some
+  int wsum[kMorseThreads / 64];
+  int nwork;               // entries of wlist
+  int total;               // staged entries
+  int flag;                // table full
+};
+
+__global__ __launch_bounds__(kMorseThreads, 4) void k_morse_force(const SimDev* __restrict__ sims, Items it, int mode) {
+  __shared__ MorseStageLds L;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  for (int item = xcd_block(); item < it.mesh_total; item += gridDim.x) {
+    const int s = find_sim(it.mesh_off, it.nsim, item);
     const SimDev& S = sims[s];
     if (mode == 0 && *S.remaining <= it.sub) continue;  // uniform over the workgroup
     if (S.morse[0] == 0.0) continue;
-    const int m = mi - it.mesh_off[s];
+    const int m = item - it.mesh_off[s];
     if (S.mesh_rigid[m]) continue;
     const int tm = S.mesh_tmpl[m], off = S.mesh_off[m], nn = S.t_nn[tm];
     const int64_t ms = (int64_t)S.maxn;
     const int par = (int)((*S.step + it.sub) & 1);
-    const GLB int32_t* gc = S.gcount + (int64_t)par * S.ngrid;
+    const GLB int32_t* gw = S.gcount + (int64_t)par * kMorseWords * S.ngrid;  // (owner, count) per cell
     const GLB int32_t* gl = S.glist + (int64_t)par * S.ngrid * kMorseCap;
-    const double D0 = S.morse[0], al = S.morse[1], r0 = S.morse[2], rc = S.morse[3];
-    for (int i = c * kMorseThreads + tid; i < nn; i += kMorseThreads * kMorseChunks) {
-      const int gid = off + i;
-      const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
-      long long wh[3] = {0, 0, 0}, wl[3] = {0, 0, 0};  // two-word sums
-      if (isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2])) {
-        int lo[3], cnt[3];
-        for (int a = 0; a < 3; ++a) {
-          const int ca = morse_axis(S, a, X[a]), ng = S.ngm[a];
-          if (ng < 3) {
-            lo[a] = 0;  // every cell once
-            cnt[a] = ng;
-          } else if (S.wall[a]) {
-            lo[a] = ca > 0 ? ca - 1 : 0;
-            cnt[a] = (ca + 1 < ng ? ca + 1 : ng - 1) - lo[a] + 1;
-          } else {
-            lo[a] = ca - 1;  // wrapped below
-            cnt[a] = 3;
+    const MorseParams P = morse_params(S);
+    bool direct = nn > kMorseNodes;  // uniform
+    if (!direct) {
+      // (1) each node marks its neighbouring cells with other capsules' nodes
+      for (int k = tid; k < kMorseSlots; k += kMorseThreads) L.key[k] = -1;
+      if (tid == 0) L.flag = L.nwork = 0;
+      __syncthreads();
+      for (int i = tid; i < nn; i += kMorseThreads) {
+        const int gid = off + i;
+        const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+        uint32_t work = 0u, mixed;
+        if (isfinite(X[0]) && isfinite(X[1]) && isfinite(X[2])) {
+          MorseCells C;
+          morse_cells(S, X, C);
+          morse_marks(S, gw, C, m, work, mixed);
+          for (uint32_t w = work; w; w &= w - 1u)
+            if (morse_slot(L.key, morse_cell(S, C, __builtin_ctz(w))) < 0) L.flag = 1;
+        }
+        L.work[i] = work;
+        // nodes with marked cells are listed for (4), so its waves hold only
+        // such nodes; the others have no pair force
+        if (work) {
+          L.wlist[atomicAdd(&L.nwork, 1)] = (int16_t)i;
+        } else {
+          const long long z[3] = {0, 0, 0};
+          morse_store(S, gid, z, z);
+        }
+      }
+      __syncthreads();
+      direct = L.flag != 0;
+    }
+    if (!direct) {
+      // (2) entries per marked cell, and their offsets in the stage (a scan
+      // over the table, two slots per thread)
+      int c2[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int k = 2 * tid + u;
+        int c = 0;
+        if (L.key[k] >= 0) {
+          c = gw[kMorseWords * (int64_t)L.key[k] + 1];
+          c = c < kMorseCap ? c : kMorseCap;
+        }
+        c2[u] = c;
+      }
+      const int v = c2[0] + c2[1];
+      int x = v;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+      }
+      if (lane == 63) L.wsum[wv] = x;
+      __syncthreads();
+      int pre = 0, total = 0;
+#pragma unroll
+      for (int k = 0; k < kMorseThreads / 64; ++k) {
+        pre += k < wv ? L.wsum[k] : 0;
+        total += L.wsum[k];
+      }
+      L.start[2 * tid] = pre + x - v;
+      L.start[2 * tid + 1] = pre + x - v + c2[0];
+      if (tid == 0) L.total = total;
+      __syncthreads();
+      direct = total > kMorseStage;  // uniform
+      if (!direct) {
+        // (3) stage the entries: ids, then positions and capsules
+        constexpr int kPer = kMorseStage / kMorseThreads;
+        int jv[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = u * kMorseThreads + tid;
+          jv[u] = -1;
+          if (e < total) {
+            int lo = 0, hi = kMorseSlots - 1;  // the last slot starting at or before e
+            while (lo < hi) {
+              const int mid = (lo + hi + 1) >> 1;
+              if (L.start[mid] <= e) lo = mid;
+              else hi = mid - 1;
+            }
+            jv[u] = gl[(int64_t)L.key[lo] * kMorseCap + (e - L.start[lo])];
           }
         }
-        for (int kz = 0; kz < cnt[2]; ++kz)
-          for (int ky = 0; ky < cnt[1]; ++ky)
-            for (int kx = 0; kx < cnt[0]; ++kx) {
-              const int cx = wrap(lo[0] + kx, S.ngm[0]), cy = wrap(lo[1] + ky, S.ngm[1]),
-                        cz = wrap(lo[2] + kz, S.ngm[2]);
-              const int64_t cell = cx + (int64_t)S.ngm[0] * (cy + (int64_t)S.ngm[1] * cz);
-              int nc = gc[cell];
-              nc = nc < kMorseCap ? nc : kMorseCap;
-              for (int k = 0; k < nc; ++k) {
-                const int j = gl[cell * kMorseCap + k];
-                if (S.node_mesh[j] == m) continue;  // the same capsule
-                double d[3], r2 = 0.0;
-                for (int a = 0; a < 3; ++a) {
-                  d[a] = X[a] - S.X[a * ms + j];
-                  if (!S.wall[a]) d[a] -= (double)S.n[a] * floor(d[a] / (double)S.n[a] + 0.5);
-                  r2 += d[a] * d[a];
-                }
-                const double r = sqrt(r2);
-                if (!(r < rc) || r == 0.0) continue;
-                const double e1 = exp(-al * (r - r0)), f = 2.0 * al * D0 * (e1 * e1 - e1) / r;
-                for (int a = 0; a < 3; ++a) morse_accumulate(S, f * d[a], wh[a], wl[a]);
-              }
-            }
-      }
-      for (int a = 0; a < 3; ++a) {
-        // carry the low word's whole multiples of 2^-44 into the high one;
-        // both words then convert exactly while |F| < 2^9
-        const long long c = wl[a] >> 52;
-        const long long h = wh[a] + c, l = wl[a] - (c << 52);
-        S.Fm[a * ms + gid] = (double)h / kMorseHi + (double)l / (kMorseHi * kMorseLo);
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int e = u * kMorseThreads + tid;
+          if (jv[u] < 0) continue;
+          const int j = jv[u];
+          L.x[0][e] = S.X[j];
+          L.x[1][e] = S.X[ms + j];
+          L.x[2][e] = S.X[2 * ms + j];
+          L.mesh[e] = S.node_mesh[j];
+        }
+        __syncthreads();
+        // (4) the listed nodes' pairs from the stage
+        for (int k = tid; k < L.nwork; k += kMorseThreads) {
+          const int i = L.wlist[k], gid = off + i;
+          long long wh[3] = {0, 0, 0}, wl[3] = {0, 0, 0};
+          uint32_t work = L.work[i];
+          const double X[3] = {S.X[gid], S.X[ms + gid], S.X[2 * ms + gid]};
+          MorseCells C;
+          morse_cells(S, X, C);
+          while (work) {
+            const int kc = __builtin_ctz(work);
+            work &= work - 1u;
+            const int sl = morse_find(L.key, morse_cell(S, C, kc));
+            const int e0 = L.start[sl], e1 = sl + 1 < kMorseSlots ? L.start[sl + 1] : L.total;
+            for (int e = e0; e < e1; ++e)
+              if (L.mesh[e] != m) morse_pair(S, P, X, L.x[0][e], L.x[1][e], L.x[2][e], wh, wl);
+          }
+          morse_store(S, gid, wh, wl);
+        }
       }
     }
+    if (direct)  // uniform
+      for (int i = tid; i < nn; i += kMorseThreads) morse_node_direct(S, P, gw, gl, m, off + i);
+    __syncthreads();  // the stage is reused by the next capsule
   }
 }
 
@@ -1048,8 +1350,9 @@ __global__ void k_morse_clear(const SimDev* __restrict__ sims, Items it) {
   for (int s = 0; s < it.nsim; ++s) {
     const SimDev& S = sims[s];
     if (S.morse[0] == 0.0) continue;
-    GLB int32_t* g = S.gcount + (int64_t)(*S.step & 1) * S.ngrid;
-    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < S.ngrid; k += (int64_t)gridDim.x * blockDim.x)
+    GLB int32_t* g = S.gcount + (int64_t)(*S.step & 1) * kMorseWords * S.ngrid;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < kMorseWords * S.ngrid;
+         k += (int64_t)gridDim.x * blockDim.x)
       g[k] = 0;
   }
 }
@@ -1499,7 +1802,7 @@ void forces_impl(const SimDev* sims, const Items& it, int mode, hipStream_t s) {
                          it, mode);
   }
   if (it.morse) {
-    const dim3 grid(grid_for(it.mesh_total * kMorseChunks, 1 << 20));
+    const dim3 grid(grid_for(it.mesh_total, 1 << 20));
     hipLaunchKernelGGL(k_morse_bin, grid, dim3(kMorseThreads), 0, s, sims, it, mode);
     hipLaunchKernelGGL(k_morse_force, grid, dim3(kMorseThreads), 0, s, sims, it, mode);
     if (mode == 1) hipLaunchKernelGGL(k_morse_clear, dim3(256), dim3(256), 0, s, sims, it);

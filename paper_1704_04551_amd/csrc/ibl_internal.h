@@ -41,6 +41,7 @@ constexpr int kMaxTemplateNodes = 4096;  // nodes per template (one workgroup pe
 constexpr int kBodyState = 16;   // doubles per rigid-body state record
 constexpr int kBodyConst = 10;   // doubles per rigid-body constants record
 constexpr int kMorseCap = 48;    // nodes per cell of the Morse neighbour grid
+constexpr int kMorseWords = 2;   // int32 words per cell of that grid (owner, count)
 
 // ------------------------------------------------------------------------
 // D3Q19 in the library's order: the rest velocity, the z = 0 plane, then the
@@ -165,7 +166,8 @@ struct SimDev {
   double morse[4];              // D0, alpha, r0, rc (D0 = 0: off)
   int32_t ngm[3];               // grid cells per axis (each at least 2 lattice units wide)
   int64_t ngrid;
-  IBL_G(int32_t) gcount;        // [2][ngrid] nodes per grid cell
+  IBL_G(int32_t) gcount;        // [2][ngrid][kMorseWords] per grid cell: owner (0 empty,
+                                //   m + 1 only mesh m's nodes, -1 several meshes'), count
   IBL_G(int32_t) glist;         // [2][ngrid][kMorseCap] node ids
   IBL_G(double) Fm;             // [3][max_nodes] Morse force of the step
   // templates

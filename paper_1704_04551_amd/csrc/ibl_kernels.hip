@@ -129,7 +129,7 @@ __global__ __launch_bounds__(kBrickThreads) void k_init(const SimDev* __restrict
     const int64_t b = item - it.lat_off[s];
     // the arena may hold a previous user's data: every list is emptied
     for (int64_t j = b * kBrickThreads + tid; j < S.ncube; j += S.nbrick * kBrickThreads) S.hcount[j] = 0;
-    for (int64_t j = b * kBrickThreads + tid; j < 2 * S.ngrid; j += S.nbrick * kBrickThreads) S.gcount[j] = 0;
+    for (int64_t j = b * kBrickThreads + tid; j < 2 * kMorseWords * S.ngrid; j += S.nbrick * kBrickThreads) S.gcount[j] = 0;
     if (tid == 0) {
       S.bcount[b] = 0;
       S.bcount[S.nbrick + b] = 0;
@@ -158,7 +158,7 @@ __global__ void k_reset_lists(const SimDev* __restrict__ sim) {
     S.bcount[b] = 0;
     S.bcount[S.nbrick + b] = 0;
   }
-  for (int64_t k = b; k < 2 * S.ngrid; k += (int64_t)gridDim.x * blockDim.x) S.gcount[k] = 0;
+  for (int64_t k = b; k < 2 * kMorseWords * S.ngrid; k += (int64_t)gridDim.x * blockDim.x) S.gcount[k] = 0;
   if (b == 0) reset_list_control(S);
 }
 

@@ -111,6 +111,9 @@ ibl_status check_desc(const ibl_sim_desc* d) {
     return fail(IBL_ERR_ARG, "brick_x must be 0, 16, 32 or 64");
   if (d->skin != 0 && d->skin != 1) return fail(IBL_ERR_ARG, "skin must be 0 or 1");
   if (d->morse != 0 && d->morse != 1) return fail(IBL_ERR_ARG, "morse must be 0 or 1");
+  if (d->morse && (int64_t)(d->n[0] / 2 > 0 ? d->n[0] / 2 : 1) * (d->n[1] / 2 > 0 ? d->n[1] / 2 : 1) *
+                          (d->n[2] / 2 > 0 ? d->n[2] / 2 : 1) >= ((int64_t)1 << 31))
+    return fail(IBL_ERR_ARG, "the Morse neighbour grid is limited to 2^31 cells");
   if (d->delta < 0 || d->delta > 1) return fail(IBL_ERR_ARG, "unknown delta kernel");
   if (d->init_profile < 0 || d->init_profile > 1) return fail(IBL_ERR_ARG, "unknown init profile");
   if (d->max_nodes < 0 || d->max_meshes < 0 || d->max_templates < 0 || d->max_template_nodes < 0 ||
@@ -186,7 +189,7 @@ Layout make_layout(const ibl_sim_desc* d) {
   L.ngrid = 0;
   for (int a = 0; a < 3; ++a) L.ngm[a] = d->morse ? (d->n[a] / 2 > 0 ? d->n[a] / 2 : 1) : 0;
   if (d->morse) L.ngrid = (int64_t)L.ngm[0] * L.ngm[1] * L.ngm[2];
-  L.gcount = take(2 * (size_t)L.ngrid * 4);
+  L.gcount = take(2 * (size_t)L.ngrid * kMorseWords * 4);
   L.glist = take(2 * (size_t)L.ngrid * kMorseCap * 4);
   L.fm = take(3 * maxn * 8);
   L.t_nn = take((size_t)d->max_templates * 4);
