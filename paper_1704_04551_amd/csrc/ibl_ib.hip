@@ -1206,6 +1206,7 @@ struct MorseStageLds {
   int16_t wlist[kMorseNodes];  // the nodes that have some
   int wsum[kMorseThreads / 64];
   int nwork;               // entries of wlist
+  int bucket[28];          // listed nodes by number of marked cells, then their offsets
   int total;               // staged entries
   int flag;                // table full
 };
@@ -1230,7 +1231,8 @@ __global__ __launch_bounds__(kMorseThreads, 4) void k_morse_force(const SimDev* 
     if (!direct) {
       // (1) each node marks its neighbouring cells with other capsules' nodes
       for (int k = tid; k < kMorseSlots; k += kMorseThreads) L.key[k] = -1;
-      if (tid == 0) L.flag = L.nwork = 0;
+      if (tid < 28) L.bucket[tid] = 0;
+      if (tid == 0) L.flag = 0;
       __syncthreads();
       for (int i = tid; i < nn; i += kMorseThreads) {
         const int gid = off + i;
@@ -1244,17 +1246,41 @@ __global__ __launch_bounds__(kMorseThreads, 4) void k_morse_force(const SimDev* 
             if (morse_slot(L.key, morse_cell(S, C, __builtin_ctz(w))) < 0) L.flag = 1;
         }
         L.work[i] = work;
-        // nodes with marked cells are listed for (4), so its waves hold only
-        // such nodes; the others have no pair force
-        if (work) {
-          L.wlist[atomicAdd(&L.nwork, 1)] = (int16_t)i;
-        } else {
+        if (!work) {  // no pair force
           const long long z[3] = {0, 0, 0};
           morse_store(S, gid, z, z);
         }
       }
       __syncthreads();
       direct = L.flag != 0;
+      // the nodes with marked cells are listed for (4), most marked cells
+      // first (a counting sort by their number), so that a wave's lanes
+      // have similar loops and its waves hold only such nodes
+      if (!direct) {
+        constexpr int kPer = kMorseNodes / kMorseThreads;
+        int rank[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int i = u * kMorseThreads + tid;
+          rank[u] = i < nn && L.work[i] ? atomicAdd(&L.bucket[__popc(L.work[i])], 1) : 0;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          int b = 0;
+          for (int k = 27; k >= 1; --k) {
+            const int c = L.bucket[k];
+            L.bucket[k] = b;
+            b += c;
+          }
+          L.nwork = b;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+          const int i = u * kMorseThreads + tid;
+          if (i < nn && L.work[i]) L.wlist[L.bucket[__popc(L.work[i])] + rank[u]] = (int16_t)i;
+        }
+      }
     }
     if (!direct) {
       // (2) entries per marked cell, and their offsets in the stage (a scan
