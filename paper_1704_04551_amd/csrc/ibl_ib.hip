@@ -14,6 +14,14 @@
 //                 one workgroup per capsule, before the force kernel: WLC-POW
 //                 stretching, area and volume constraints summed per node in
 //                 fixed point; the force kernels add the result.
+//   k_morse_bin / k_morse_force  (simulations with the repulsion of Eq. (13))
+//                 one workgroup per capsule: the capsule nodes binned into a
+//                 neighbour grid, then each node's pair forces from the other
+//                 capsules' nodes in its 27 neighbouring cells, staged in LDS;
+//                 the force kernels add the result.
+//   k_rigid_nodes / k_rigid_body  (rigid bodies, Eq. (17)) the node forces
+//                 from the interpolated fluid velocity, then per body the
+//                 force and torque and the Newton-Euler update.
 //   Each force kernel writes the node's spreading record (stencil base,
 //   fractional offset or delta weights, F), adds the step's largest force
 //   component to the simulation's maximum, and appends the node to the
