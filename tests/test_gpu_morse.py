@@ -177,3 +177,46 @@ def test_morse_stage_overflow():
     capsule, so both fall back to global reads.  Same checks, 20 steps."""
     spec = _pair_spec(3, (5.0, 5.6), ((8.0, 8.0, 7.9), (8.0, 8.0, 7.9)), (16, 16, 16), 2.4e-5, "morse-nested")
     _check_forces_and_steps(spec, 20)
+
+
+def test_morse_full_size_sampled():
+    """The RBC channel at full size (256x128x128, 1018 cells, 653,556 nodes)
+    with the repulsion at the paper's constants (Sec. 3.5 table in lattice
+    units: D0 = 2.4e-5, alpha = 0.25, r0 = rc = 1.32), in the bench's launch
+    configuration (FP32, 64-wide bricks).  At time 0 each node's Morse force
+    is its force with the repulsion minus its force without (the membrane
+    part, at the cells' rest shape, is the same bitwise).  Every node in four
+    boxes 16 lu wide is checked against the oracle's pair sums over the nodes
+    of the box widened by 2 lu (more than rc), within 1e-12 of the largest
+    force."""
+    import dataclasses
+    from oracle import morse as oracle_morse
+    D0, al, r0, rc = 2.4e-5, 0.25, 1.32, 1.32
+    base = W.config_rbc_channel()
+    assert base.nodes == 653556
+    Fs = []
+    for mo in ((), (D0, al, r0, rc)):
+        spec = dataclasses.replace(base, morse=mo)
+        g = ibl.Sim.from_spec(spec, storage="f32", brick_x=64, skin=0)
+        nodes = [g.nodes(m) for m in range(len(spec.capsules))]
+        assert g.conservation()[2] == 0
+        g.close()
+        Fs.append(np.concatenate([f for _, _, f in nodes]))
+    X = np.concatenate([x for x, _, _ in nodes])
+    F = Fs[1] - Fs[0]
+    obj = np.concatenate([np.full(len(c.x), m) for m, c in enumerate(spec.capsules)])
+    n = np.asarray(spec.n, float)
+    rng = np.random.default_rng(5)
+    checked = hit = 0
+    for centre in X[rng.choice(len(X), 4, replace=False)]:
+        d = X - centre
+        d[:, 0] -= n[0] * np.round(d[:, 0] / n[0])  # periodic x: the nearest image
+        crop = np.all(np.abs(d) <= 10.0, axis=1)
+        inner = np.all(np.abs(d[crop]) <= 8.0, axis=1)
+        Fo, _ = oracle_morse(spec.n, centre + d[crop], obj[crop], D0, al, r0, rc, wall=spec.wall)
+        Fg = F[crop][inner]
+        scale = max(np.abs(Fo[inner]).max(), 1e-30)
+        assert np.abs(Fg - Fo[inner]).max() <= 1e-12 * scale + 1e-300
+        checked += int(inner.sum())
+        hit += int(np.any(Fo[inner] != 0.0, axis=1).sum())
+    assert checked > 1000 and hit > 0, (checked, hit)
