@@ -304,9 +304,31 @@ __global__ void k_set_many(StepArgs a) {
   if (i < a.n) *a.ptr[i] = a.val[i];
 }
 
+// The graphs a run of `nmax` steps replays.  The first call that needs one
+// not yet captured captures every size, so that later runs of any length
+// only replay.
+ibl_status ensure_graphs(int storage, const SimDev* sims, const Items& it, hipStream_t s, GraphSet& G,
+                         int64_t nmax) {
+  if (nmax <= 0) return IBL_OK;
+  const int64_t full = nmax / kGraphSteps;
+  const int rem = (int)(nmax % kGraphSteps);
+  bool missing = false;
+  for (int k = GraphSet::kSizes - 1; k >= 0; --k) {
+    const int len = 1 << k;
+    const bool need = (len == kGraphSteps) ? full > 0 : (rem & len) != 0;
+    missing |= need && !G.g[k];
+  }
+  for (int k = GraphSet::kSizes - 1; missing && k >= 0; --k)
+    if (!G.g[k]) {
+      ibl_status st = capture(storage, sims, it, s, 1 << k, &G.g[k]);
+      if (st) return st;
+    }
+  return IBL_OK;
+}
+
 // Run `n` steps (remaining <- n on every simulation of the set, set by the
-// caller): replay the 16-step graph n / 16 times, then one graph of each
-// power of two in the binary expansion of n % 16.
+// caller): replay the 16-step graph n / 16 times, then
+// one graph of each power of two in the binary expansion of n % 16.
 ibl_status run_steps(int storage, const SimDev* sims, const Items& it, hipStream_t s, GraphSet& G,
                      int64_t nmax) {
   if (nmax <= 0) return IBL_OK;
@@ -315,7 +337,7 @@ ibl_status run_steps(int storage, const SimDev* sims, const Items& it, hipStream
   for (int k = GraphSet::kSizes - 1; k >= 0; --k) {
     const int len = 1 << k;
     const bool need = (len == kGraphSteps) ? full > 0 : (rem & len) != 0;
-    if (need && !G.g[k]) {
+    if (need && !G.g[k]) {  // (ensure_graphs captured them)
       ibl_status st = capture(storage, sims, it, s, len, &G.g[k]);
       if (st) return st;
     }
@@ -1037,6 +1059,8 @@ ibl_status ibl_step(ibl_sim S, int64_t n) {
   if (!S || n < 0) return fail(IBL_ERR_ARG, "bad argument");
   if (n == 0) return IBL_OK;
   HIPCHK(hipSetDevice(S->device));
+  ibl_status st = ensure_graphs(S->desc.storage, S->dd, S->items, S->stream, S->graphs, n);
+  if (st) return st;
   hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, S->stream, S->hd.remaining, n);
   HIPCHK(hipGetLastError());
   return run_steps(S->desc.storage, S->dd, S->items, S->stream, S->graphs, n);
@@ -1358,6 +1382,10 @@ ibl_status ibl_batch_step(ibl_batch B, const int64_t* steps) {
       HIPCHK(hipEventRecord(B->ev, B->sims[i]->stream));
       HIPCHK(hipStreamWaitEvent(B->stream, B->ev, 0));
     }
+  {
+    ibl_status st = ensure_graphs(B->storage, B->dsims, B->items, B->stream, B->graphs, nmax);
+    if (st) return st;
+  }
   for (int i0 = 0; i0 < n; i0 += 64) {
     StepArgs a;
     a.n = (n - i0) < 64 ? (n - i0) : 64;
