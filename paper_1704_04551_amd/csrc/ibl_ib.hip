@@ -927,9 +927,10 @@ __global__ __launch_bounds__(256) void k_node_forces(const SimDev* __restrict__ 
 //                  into two 64-bit fixed-point words (units 2^-44 and 2^-96)
 //                  and summed as integers: the sum is exact to 2^-96 per pair
 //                  and does not depend on the order of the cell lists, and the
-//                  two nodes of a pair get exact opposites.  A capsule whose
-//                  marked cells overflow the LDS stage reads them from global
-//                  memory node by node instead (the same pairs and sums).
+//                  two nodes of a pair get exact opposites.  A capsule of
+//                  more than 1024 nodes, or whose marked cells or their nodes
+//                  overflow the LDS tables, reads them from global memory node
+//                  by node instead (the same pairs and sums).
 //   k_morse_clear  an observation's grid, emptied after it (the next step
 //                  bins into the same parity).
 constexpr int kMorseThreads = 256;
